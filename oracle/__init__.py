@@ -1,0 +1,197 @@
+"""FP64 CPU oracle for Reduced Basis Decomposition (test infrastructure only).
+
+This package is the independent reference the device path is checked
+against.  It is test infrastructure: only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import it; the library never does, and the
+two share no code (the only shared module is ``synth``, which holds input
+generators and storage rounding, none of the method's arithmetic).
+
+Contents
+--------
+``rbd_fit``      Algorithm 1 of the paper (section 3.1), step by step, in FP64:
+                 explicit residual, errors evaluated by their definition in
+                 step 2.3 (no downdating), Gram-Schmidt done twice.
+``rbd_brute``    Brute-force greedy for tiny inputs: every step re-derives each
+                 column's projection error from a fresh QR of the chosen
+                 columns (section 3.1, step 2.3 by definition).
+``rbd_project``  Out-of-sample compression v_C = Y' v (section 3.1, "Evaluate
+                 the compression of out-of-sample data") with the A = I error
+                 of eq. (3) evaluated as the norm of the explicit residual.
+
+Readings where the paper is silent or ambiguous (each is listed with its
+reason in the design notes):
+  * first column: ``start < 0`` takes the lowest index of max_j ||x_j||
+    (a deterministic stand-in for the random start of step 1);
+  * argmax ties go to the lowest index;
+  * a column already chosen as a pivot has error exactly 0;
+  * orthonormalisation is modified Gram-Schmidt applied twice;
+  * the truncation in step 2.2 keeps the first d-1 *rows* of T;
+  * a zero vector (norm exactly 0) also ends the loop, since it cannot be
+    normalised even when the tolerance is 0;
+  * relative tolerance: tau = tol * max_j ||x_j||.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class OracleFit:
+    Y: np.ndarray          # (m, d) orthonormal basis
+    T: np.ndarray          # (d, n) transformation, T = Y' X
+    pivots: np.ndarray     # (d,) 0-based column chosen at each step
+    col_err: np.ndarray    # (n,) ||x_j - Y T(:, j)||, 0 for pivots
+    err_hist: np.ndarray   # (d+1,) E_0 = max_j ||x_j||, then E_k after step k
+    gap_hist: np.ndarray   # (d+1,) (largest - second largest unmasked error) / E_0 before each pick
+    d: int
+    tau: float
+    stop: str              # "tol" | "dmax" | "break"
+
+
+def _colnorms(R: np.ndarray) -> np.ndarray:
+    """Euclidean norm of every column, summed in FP64."""
+    return np.sqrt(np.einsum("ij,ij->j", R, R))
+
+
+def _lowest_argmax(e: np.ndarray) -> int:
+    """Lowest index attaining the maximum (numpy's argmax returns the first one)."""
+    return int(np.argmax(e))
+
+
+def _gap(e: np.ndarray, E0: float) -> float:
+    if e.size < 2 or E0 == 0.0:
+        return np.inf
+    top2 = np.partition(e, e.size - 2)[-2:]
+    return float((top2[1] - top2[0]) / E0)
+
+
+def project_row(xi: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Step 2.2, last line: the new row of T is xi' X."""
+    return xi @ X
+
+
+def residual_update(R: np.ndarray, xi: np.ndarray, t: np.ndarray) -> None:
+    """R <- R - xi t', so that R = X - Y(:, 1:d) T(1:d, :) holds after step d."""
+    R -= np.outer(xi, t)
+
+
+def mgs_twice(v: np.ndarray, Y: np.ndarray, d: int) -> np.ndarray:
+    """Step 2.2: modified Gram-Schmidt of v against xi_1..xi_{d-1}, applied twice."""
+    v = v.copy()
+    for _ in range(2):
+        for k in range(d):
+            v -= (Y[:, k] @ v) * Y[:, k]
+    return v
+
+
+def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1) -> OracleFit:
+    """Algorithm 1, (Y, T) = RBD(X, eps_R, d_max), with A = I (section 3.1).
+
+    ``X`` must already hold the stored values (e.g. FP32- or BF16-rounded data
+    upcast to FP64).  Returns the first ``d`` basis vectors, rows of T, pivots,
+    final per-column errors and the error history.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    if X.ndim != 2:
+        raise ValueError("X must be a matrix")
+    m, n = X.shape
+    if m < 1 or n < 1 or d_max < 1:
+        raise ValueError("empty input or d_max < 1")
+    if not np.all(np.isfinite(X)):
+        raise FloatingPointError("X holds a non-finite value")
+    D = min(int(d_max), m, n)
+
+    # pre-computation of diag(X'X): the error of every column with d = 0
+    e = _colnorms(X)
+    E0 = float(e.max())
+    tau = float(tol) * E0 if rel else float(tol)
+
+    Y = np.zeros((m, D))
+    T = np.zeros((D, n))
+    R = X.copy()                        # residual X - Y T, kept explicitly
+    chosen = np.zeros(n, dtype=bool)
+    pivots = []
+    err_hist = [E0]
+    gap_hist = [_gap(e, E0)]
+
+    # step 1
+    i = int(start) if start >= 0 else _lowest_argmax(e)
+    if not 0 <= i < n:
+        raise ValueError("start column out of range")
+    d = 0                               # number of accepted basis vectors (paper's d - 1)
+    E_cur = np.inf
+    stop = "dmax"
+
+    # step 2: while d <= d_max and E_cur > eps_R  (paper's d is our d + 1)
+    while d < D and E_cur > tau:
+        v = X[:, i].copy()                              # 2.1
+        v = mgs_twice(v, Y, d)                          # 2.2
+        nu = float(np.sqrt(v @ v))
+        if nu < tau or nu == 0.0:
+            stop = "break"                              # keep d columns (paper's d - 1)
+            break
+        xi = v / nu
+        Y[:, d] = xi
+        T[d, :] = project_row(xi, X)
+        residual_update(R, xi, T[d, :])
+        chosen[i] = True
+        pivots.append(i)
+        d += 1
+        # 2.3: errors by their definition, pivots masked
+        e = _colnorms(R)
+        e[chosen] = 0.0
+        E_cur = float(e.max())
+        gap_hist.append(_gap(e[~chosen], E0) if (~chosen).sum() >= 2 else np.inf)
+        i = _lowest_argmax(e)
+        err_hist.append(E_cur)
+        # 2.4
+        if E_cur <= tau:
+            stop = "tol"
+    return OracleFit(Y=Y[:, :d].copy(), T=T[:d].copy(), pivots=np.array(pivots, dtype=np.int64),
+                     col_err=e, err_hist=np.array(err_hist),
+                     gap_hist=np.array(gap_hist), d=d, tau=tau, stop=stop)
+
+
+def rbd_brute(X, steps: int, start: int = -1):
+    """Greedy pivots by brute force: at each step every column's projection error
+    onto span(X[:, pivots]) is recomputed from a fresh QR (step 2.3 by definition).
+
+    Returns (pivots, errors) where errors[k] is the largest error after k pivots.
+    Meant for tiny X only.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[1]
+
+    def first_max(vals):
+        top = max(vals)
+        return min(j for j, val in enumerate(vals) if val == top)
+
+    piv = []
+    e = [float(np.linalg.norm(X[:, j])) for j in range(n)]
+    errs = [max(e)]
+    nxt = int(start) if start >= 0 else first_max(e)
+    for _ in range(steps):
+        piv.append(nxt)
+        Q, _r = np.linalg.qr(X[:, piv])
+        e = [0.0 if j in piv else float(np.linalg.norm(X[:, j] - Q @ (Q.T @ X[:, j])))
+             for j in range(n)]
+        errs.append(max(e))
+        nxt = first_max(e)
+    return np.array(piv, dtype=np.int64), np.array(errs)
+
+
+def rbd_project(Y, V):
+    """Out-of-sample compression c = Y' v for every column v of V (section 3.1),
+    with the A = I error of eq. (3) taken as ||v - Y c|| by its definition."""
+    Y = np.asarray(Y, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    C = Y.T @ V
+    err = _colnorms(V - Y @ C)
+    return C, err
+
+
+def reconstruct(Y, T):
+    """Uncompress: X(:, j) ~ Y T(:, j) (section 3.1)."""
+    return np.asarray(Y, dtype=np.float64) @ np.asarray(T, dtype=np.float64)

@@ -1,0 +1,316 @@
+"""Seeded synthetic inputs for the reduced-basis-decomposition hot path.
+
+This module is shared by the FP64 oracle (``oracle/``), the tests and the
+benchmark.  It holds input generators and storage-precision rounding only:
+none of the decomposition's own arithmetic (no Gram-Schmidt, no projection,
+no error evaluation, no pivot search) lives here.
+
+Every generator draws from ``numpy.random.default_rng(SeedSequence([cfg,
+seed, stream]))`` with a fixed stream id per quantity, so a workload is a
+pure function of ``(cfg, seed)``:
+
+    stream 0  left orthonormal factor U     stream 4  decay rates mu
+    stream 1  right orthonormal factor V    stream 5  fixed centres c_k
+    stream 2  additive noise                stream 6  cotangent G
+    stream 3  bump parameters               stream 7  batch sizes
+
+Workloads (the data model is X in R^{m x n}, columns are the samples, as in
+eq. (1) of the paper):
+
+* ``lowrank_spectrum``   -- X = U diag(sigma) V^T + noise, sigma_i = 10^(-i/4)
+  for i < 32 (512 x 256, the small parity case).
+* ``bump_field``         -- a sum of 50 random 2-D Gaussian bumps sampled on a
+  grid; column j is the slice at s2 = j/(n-1) (image-like stand-in for the
+  paper's 512 x 512 test images, whose pixels are not available).
+* ``parametric_field``   -- x(s; mu) = sum_{k<8} exp(-mu_k |s - c_k|^2) on a
+  g x g grid, one column per parameter draw (the parametric-snapshot workload
+  that motivates the method in section 2 of the paper).
+* ``table3``             -- the three separable functions of Table 3.
+* ``approx_field``       -- f = 0.6 f1 + 0.1 f2 + 0.01 f3 of section 4.2.2.
+* ``batched_spectra``    -- many small matrices with a 10^(-i/8) spectrum.
+
+Storage rounding (``quantize``) defines the exact values a reduced-precision
+X holds: FP64 -> FP32 round-to-nearest-even, then (for BF16) FP32 -> BF16
+round-to-nearest-even on the bit pattern, or FP64 -> FP16 round-to-nearest-
+even.  Both the oracle and the device path consume these stored values.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ----------------------------------------------------------------------------
+# seeding
+# ----------------------------------------------------------------------------
+
+S_U, S_V, S_NOISE, S_BUMPS, S_MU, S_CENTRES, S_G, S_SIZES = range(8)
+
+
+def rng(cfg: int, seed: int, stream: int) -> np.random.Generator:
+    """Counter-free, platform-independent generator for one (cfg, seed, stream)."""
+    return np.random.default_rng(np.random.SeedSequence([int(cfg), int(seed), int(stream)]))
+
+
+def haar(g: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    """Random matrix with orthonormal columns (QR of a Gaussian, diag(R) > 0)."""
+    a = g.standard_normal((rows, cols))
+    q, r = np.linalg.qr(a)
+    s = np.sign(np.diag(r))
+    s[s == 0] = 1.0
+    return q * s[None, :]
+
+
+@dataclass
+class Workload:
+    """An input matrix plus the fit settings it is quoted with."""
+
+    name: str
+    X: np.ndarray                 # FP64 values before storage rounding
+    tol: float
+    rel: bool                     # tau = tol * max_j ||x_j|| when True
+    d_max: int
+    meta: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------
+# storage precision
+# ----------------------------------------------------------------------------
+
+DTYPES = ("f64", "f32", "bf16", "f16")
+
+
+def bf16_bits_from_f32(a32: np.ndarray) -> np.ndarray:
+    """Round FP32 values to BF16 (nearest, ties to even); returns uint16 bit patterns."""
+    u = np.ascontiguousarray(a32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = (u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)
+    return r.astype(np.uint16)
+
+
+def bf16_bits_to_f64(bits: np.ndarray) -> np.ndarray:
+    u = bits.astype(np.uint32) << np.uint32(16)
+    return u.view(np.float32).astype(np.float64)
+
+
+def quantize(X: np.ndarray, dtype: str):
+    """Round X to a storage dtype.
+
+    Returns ``(stored, values)``: ``stored`` is the array in its storage form
+    (float64 / float32 / uint16 BF16 bit patterns / float16), ``values`` the
+    exact stored values as FP64 (what every consumer must treat as the data).
+    """
+    X = np.asarray(X, dtype=np.float64)
+    if dtype == "f64":
+        s = np.ascontiguousarray(X)
+        return s, s
+    if dtype == "f32":
+        s = np.ascontiguousarray(X.astype(np.float32))
+        return s, s.astype(np.float64)
+    if dtype == "bf16":
+        s = bf16_bits_from_f32(X.astype(np.float32))
+        return s, bf16_bits_to_f64(s)
+    if dtype == "f16":
+        s = np.ascontiguousarray(X.astype(np.float16))
+        return s, s.astype(np.float64)
+    raise ValueError(f"unknown storage dtype {dtype!r}")
+
+
+# ----------------------------------------------------------------------------
+# 1. low-rank spectrum (512 x 256, rank 32 + 1e-10 noise)
+# ----------------------------------------------------------------------------
+
+def lowrank_spectrum(seed: int = 0, m: int = 512, n: int = 256, r: int = 32,
+                     decade: float = 4.0, noise: float = 1e-10) -> Workload:
+    """X = U diag(10^(-i/decade)) V^T + noise * N(0,1); noise is a standard deviation."""
+    U = haar(rng(1, seed, S_U), m, r)
+    V = haar(rng(1, seed, S_V), n, r)
+    sig = 10.0 ** (-np.arange(r) / decade)
+    X = (U * sig[None, :]) @ V.T
+    if noise:
+        X = X + noise * rng(1, seed, S_NOISE).standard_normal((m, n))
+    return Workload("lowrank_spectrum", X, tol=1e-8, rel=False, d_max=64,
+                    meta=dict(m=m, n=n, rank=r, sigma=sig))
+
+
+def random_rank(seed: int, m: int, n: int, r: int) -> np.ndarray:
+    """Random exactly-rank-r matrix (Gaussian factors, no noise)."""
+    g = rng(90, seed, S_U)
+    return g.standard_normal((m, r)) @ g.standard_normal((r, n))
+
+
+# ----------------------------------------------------------------------------
+# 2. bump field (image-like, 2048 x 2048)
+# ----------------------------------------------------------------------------
+
+def bump_params(seed: int, count: int = 50, cfg: int = 2):
+    g = rng(cfg, seed, S_BUMPS)
+    centres = g.uniform(0.0, 1.0, size=(count, 2))
+    widths = g.uniform(0.02, 0.2, size=count)
+    amps = g.standard_normal(count)
+    return centres, widths, amps
+
+
+def bump_field(seed: int = 0, m: int = 2048, n: int = 2048, noise: float = 1e-4,
+               cfg: int = 2, tol: float = 1e-4, d_max: int = 256) -> Workload:
+    """F(s1, s2) = sum_b a_b exp(-|s - c_b|^2 / (2 w_b^2)) + noise, s1 = i/(m-1), s2 = j/(n-1).
+
+    Each bump is separable, so X is accumulated as rank-1 terms in a fixed
+    order (elementwise IEEE arithmetic: identical on every host).
+    """
+    centres, widths, amps = bump_params(seed, cfg=cfg)
+    s1 = np.arange(m, dtype=np.float64) / max(m - 1, 1)
+    s2 = np.arange(n, dtype=np.float64) / max(n - 1, 1)
+    X = np.zeros((m, n))
+    for (c1, c2), w, a in zip(centres, widths, amps):
+        g1 = np.exp(-((s1 - c1) ** 2) / (2.0 * w * w))
+        g2 = np.exp(-((s2 - c2) ** 2) / (2.0 * w * w))
+        X += (a * g1)[:, None] * g2[None, :]
+    if noise:
+        X += noise * rng(cfg, seed, S_NOISE).standard_normal((m, n))
+    return Workload("bump_field", X, tol=tol, rel=True, d_max=d_max,
+                    meta=dict(m=m, n=n, bumps=len(amps)))
+
+
+# ----------------------------------------------------------------------------
+# 3. parametric field (1,048,576 x 4096 at full size)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ParametricField:
+    """x_j(s) = sum_{k<8} exp(-mu_{j,k} |s - c_k|^2), s = (a/(g-1), b/(g-1)), row = g*a + b."""
+
+    mu: np.ndarray        # (n, K) decay rates, U[1, 100]
+    centres: np.ndarray   # (K, 2) fixed centres, U[0.1, 0.9]^2
+    grid: int             # g: the grid is g x g, m = g*g
+
+    @property
+    def m(self) -> int:
+        return self.grid * self.grid
+
+    @property
+    def n(self) -> int:
+        return self.mu.shape[0]
+
+    def factors(self, cols=None):
+        """Separable factors A[k, a, j] = exp(-mu_jk (a/(g-1) - c_k1)^2), B likewise with c_k2."""
+        mu = self.mu if cols is None else self.mu[cols]
+        s = np.arange(self.grid, dtype=np.float64) / (self.grid - 1)
+        K = mu.shape[1]
+        A = np.empty((K, self.grid, mu.shape[0]))
+        B = np.empty((K, self.grid, mu.shape[0]))
+        for k in range(K):
+            A[k] = np.exp(-mu[None, :, k] * ((s[:, None] - self.centres[k, 0]) ** 2))
+            B[k] = np.exp(-mu[None, :, k] * ((s[:, None] - self.centres[k, 1]) ** 2))
+        return A, B
+
+    def rows(self, idx, A=None, B=None) -> np.ndarray:
+        """FP64 values of the given rows (all columns), same operation order as ``fill_device``."""
+        idx = np.asarray(idx, dtype=np.int64)
+        if A is None:
+            A, B = self.factors()
+        a, b = idx // self.grid, idx % self.grid
+        out = A[0][a] * B[0][b]
+        for k in range(1, A.shape[0]):
+            out = out + A[k][a] * B[k][b]
+        return out
+
+    def full(self) -> np.ndarray:
+        A, B = self.factors()
+        return self.rows(np.arange(self.m), A, B)
+
+    def fill_device(self, out, rows_per_chunk: int = 16 * 1024):
+        """Write the stored values into a device tensor ``out`` (m x n, f32/bf16/f16/f64).
+
+        Elementwise FP64 multiplies and adds in the same order as ``rows`` (so the
+        values are bit-identical to the host's), then one rounding to FP32 and,
+        for BF16/F16, a second rounding from FP32 as torch defines it.  This is
+        input generation, not part of the decomposition.
+        """
+        import torch
+
+        dev = out.device
+        A, B = self.factors()
+        At = torch.from_numpy(A).to(dev)
+        Bt = torch.from_numpy(B).to(dev)
+        g = self.grid
+        per = max(1, rows_per_chunk // g)
+        for a0 in range(0, g, per):
+            a1 = min(g, a0 + per)
+            acc = At[0, a0:a1, None, :] * Bt[0, None, :, :]
+            for k in range(1, At.shape[0]):
+                acc = acc + At[k, a0:a1, None, :] * Bt[k, None, :, :]
+            acc = acc.reshape((a1 - a0) * g, -1)
+            if out.dtype == torch.float64:
+                out[a0 * g:a1 * g] = acc
+            elif out.dtype == torch.float32:
+                out[a0 * g:a1 * g] = acc.to(torch.float32)
+            else:
+                out[a0 * g:a1 * g] = acc.to(torch.float32).to(out.dtype)
+            del acc
+        del At, Bt
+
+
+def parametric_field(seed: int = 0, grid: int = 1024, n: int = 4096, K: int = 8) -> ParametricField:
+    mu = rng(3, seed, S_MU).uniform(1.0, 100.0, size=(n, K))
+    centres = rng(3, 0, S_CENTRES).uniform(0.1, 0.9, size=(K, 2))   # fixed across seeds
+    return ParametricField(mu=mu, centres=centres, grid=grid)
+
+
+# ----------------------------------------------------------------------------
+# Table 3 and section 4.2.2 functions (uniform grid on [-1, 1]^2)
+# ----------------------------------------------------------------------------
+
+def grid_11(n: int) -> np.ndarray:
+    return -1.0 + 2.0 * np.arange(n, dtype=np.float64) / (n - 1)
+
+
+def table3(which: int, n: int = 512) -> np.ndarray:
+    """The separable functions of Table 3; rows follow x, columns follow y."""
+    x = grid_11(n)[:, None]
+    y = grid_11(n)[None, :]
+    f = np.sin(np.pi * x) * np.cos(np.pi * y)
+    if which >= 2:
+        f = f + 0.1 * np.sin(10 * np.pi * x) * np.cos(10 * np.pi * y)
+    if which >= 3:
+        f = f + 0.01 * np.sin(100 * np.pi * x) * np.cos(100 * np.pi * y)
+    return f
+
+
+def approx_field(n: int = 5001) -> np.ndarray:
+    """f = 0.6 f1 + 0.1 f2 + 0.01 f3 on an n x n grid over [-1, 1]^2 (section 4.2.2)."""
+    x = grid_11(n)[:, None]
+    y = grid_11(n)[None, :]
+    f1 = np.sin(np.pi * (x + 2 * y)) * np.cos(np.pi * (2 * x - y))
+    f2 = np.sin(10 * np.pi * (x - 3 * y)) * np.cos(10 * np.pi * (3 * x + y))
+    f3 = np.sin(3 * np.pi * x * x * y) * np.cos(6 * np.pi * np.sqrt(np.abs(x)) / (y + 2))
+    return 0.6 * f1 + 0.1 * f2 + 0.01 * f3
+
+
+# ----------------------------------------------------------------------------
+# batched small matrices (4096 matrices, m, n log-uniform in [64, 1024])
+# ----------------------------------------------------------------------------
+
+def batched_sizes(seed: int = 0, count: int = 4096, lo: int = 64, hi: int = 1024):
+    g = rng(4, seed, S_SIZES)
+    m = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+    n = np.rint(np.exp(g.uniform(math.log(lo), math.log(hi), size=count))).astype(np.int64)
+    return m, n
+
+
+def batched_matrix(seed: int, index: int, m: int, n: int, decade: float = 8.0) -> np.ndarray:
+    """X_b = U diag(10^(-i/decade)) V^T with orthonormal U, V of rank min(m, n)."""
+    r = min(m, n)
+    U = haar(rng(4, seed * 1_000_003 + index, S_U), m, r)
+    V = haar(rng(4, seed * 1_000_003 + index, S_V), n, r)
+    sig = 10.0 ** (-np.arange(r) / decade)
+    return (U * sig[None, :]) @ V.T
+
+
+# ----------------------------------------------------------------------------
+# differentiation workload (bump field at 65536 x 2048 plus a cotangent)
+# ----------------------------------------------------------------------------
+
+def cotangent(seed: int, m: int, n: int) -> np.ndarray:
+    return rng(5, seed, S_G).standard_normal((m, n))
