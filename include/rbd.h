@@ -1,0 +1,153 @@
+/*
+ * rbd.h -- C ABI of the MI355X (gfx950) Reduced Basis Decomposition library.
+ *
+ * Reduced Basis Decomposition (Y. Chen, "Reduced Basis Decomposition: a
+ * Certified and Fast Lossy Data Compression Algorithm") approximates a data
+ * matrix X (m x n, one sample per column, eq. (1)) by Y T, where Y (m x d) has
+ * orthonormal columns built greedily and T = Y'X (d x n).  Algorithm 1 of
+ * section 3.1 adds, at each step, the column of X whose projection error onto
+ * span(Y) is largest, after Gram-Schmidt orthonormalisation against Y.  With
+ * the identity weight (A = I in eq. (3)) the squared error of column j is
+ * ||x_j||^2 - ||T(:, j)||^2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers to caller-owned memory.  The
+ *    library never allocates or frees device memory and never synchronises
+ *    the stream; every call is stream-ordered on `stream` (a hipStream_t,
+ *    NULL for the legacy default stream).
+ *  - Matrices are row-major with an explicit leading dimension (elements
+ *    between consecutive rows).  Indices are 0-based.
+ *  - The synchronous return value reports argument validation and launch
+ *    errors only.  Conditions found on the device (non-finite data) are
+ *    written to the `status` word in device memory; read it after the stream
+ *    has completed.
+ *  - Calls on different streams are independent as long as they use
+ *    different workspaces and outputs.  Results are bitwise reproducible
+ *    for identical inputs on the same device (all reductions run in a fixed
+ *    order; no floating-point atomics).
+ */
+#ifndef RBD_H_
+#define RBD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage type of X (and V).  Arithmetic is always FP64: stored values are
+ * widened exactly, products and sums are formed in FP64. */
+typedef enum {
+    RBD_F32 = 0,
+    RBD_BF16 = 1, /* bfloat16 bit patterns (uint16) */
+    RBD_F16 = 2,  /* IEEE binary16 */
+    RBD_F64 = 3
+} rbd_dtype;
+
+/* How `tol` is read: RBD_TOL_ABS uses tau = tol, RBD_TOL_REL uses
+ * tau = tol * max_j ||x_j|| (the largest error before the first step). */
+typedef enum { RBD_TOL_ABS = 0, RBD_TOL_REL = 1 } rbd_tol_mode;
+
+/* Return / status codes. */
+enum {
+    RBD_OK = 0,
+    RBD_EINVAL = -1,      /* bad pointer, size, leading dimension or option      */
+    RBD_ENONFINITE = -2,  /* X holds NaN or Inf (device status only)              */
+    RBD_EWORKSPACE = -3,  /* workspace smaller than the size query returned       */
+    RBD_EDEVICE = -4      /* a HIP launch or runtime call failed                  */
+};
+
+/* Why the greedy loop ended (written to stop_reason when non-NULL). */
+enum {
+    RBD_STOP_TOL = 1,     /* step 2.4: largest error <= tau                      */
+    RBD_STOP_DMAX = 2,    /* d reached min(d_max, m, n)                           */
+    RBD_STOP_BREAK = 3    /* step 2.2: ||v|| < tau (or ||v|| = 0) after GS        */
+};
+
+/* Largest basis size supported by rbd_fit (registers hold one row of Y). */
+#define RBD_MAX_D 1024
+
+/*
+ * rbd_fit_workspace_size -- bytes of device workspace rbd_fit needs.
+ * Arguments as for rbd_fit.  Returns RBD_OK and sets *bytes, or RBD_EINVAL.
+ */
+int rbd_fit_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes);
+
+/*
+ * rbd_fit -- Algorithm 1, (Y, T) = RBD(X, eps_R, d_max), with A = I
+ * (section 3.1; error evaluation of section 3.2, eq. (3)).
+ *
+ *   X        m x n, row-major, leading dimension ldx >= n, storage type xt.
+ *   tol      eps_R >= 0, read according to `mode`.
+ *   d_max    1 <= d_max; the loop runs at most D = min(d_max, m, n) steps,
+ *            and D must not exceed RBD_MAX_D.
+ *   start    first column (step 1); start < 0 takes the lowest index of
+ *            max_j ||x_j|| (the first step of column-pivoted QR).
+ *
+ * Outputs (device memory, caller-owned, written in full):
+ *   Y        m x d_max row-major (ld = d_max), FP64.  Columns 0..d-1 hold
+ *            the orthonormal basis xi_1..xi_d; columns >= d are zeroed.
+ *   T        d_max x n row-major (ld = n), FP64; T(k, :) = xi_k' X; rows >= d
+ *            are zeroed.
+ *   pivots   d_max int64; pivots[k] = column used at step k+1; -1 after d.
+ *   col_err  n FP64; ||x_j - Y T(:, j)|| for the final d (0 for pivots).
+ *            Certified: the downdated value ||x_j||^2 - sum_k T(k,j)^2 is
+ *            replaced by an exact evaluation of the residual whenever it has
+ *            fallen below 2^-20 of the last exact value, so cancellation
+ *            never decides a step.
+ *   err_hist d_max+1 FP64; err_hist[0] = max_j ||x_j||, err_hist[k] = the
+ *            largest error after step k (E_cur of step 2.3); 0 after d.
+ *   d_out    one int32: d, the number of basis vectors kept.
+ *   status   one int32: RBD_OK or RBD_ENONFINITE.
+ *   stop_reason  one int32 (may be NULL): an RBD_STOP_* value, 0 if d = 0
+ *            because of a non-finite input.
+ *   workspace    at least rbd_fit_workspace_size() bytes, 256-byte aligned.
+ *   stream       hipStream_t (as void*).
+ *
+ * Returns RBD_OK, RBD_EINVAL, RBD_EWORKSPACE or RBD_EDEVICE.
+ */
+int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
+            double tol, rbd_tol_mode mode, int32_t d_max, int64_t start,
+            double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+            int32_t* d_out, int32_t* status, int32_t* stop_reason,
+            void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rbd_project_workspace_size -- bytes of workspace rbd_project needs.
+ */
+int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes);
+
+/*
+ * rbd_project -- out-of-sample compression (section 3.1, "Evaluate the
+ * compression of out-of-sample data"): v_C = Y' v for each column v of V,
+ * with the A = I error of eq. (3), ||v - Y v_C||, as the error indicator.
+ *
+ *   Y        m x d row-major FP64 with leading dimension ldy >= d; columns are
+ *            assumed orthonormal (as rbd_fit returns them).
+ *   V        m x k row-major, leading dimension ldv >= k, storage type vt.
+ *   Tv       d x k row-major FP64 (ld = k): the coordinates Y'V.
+ *   err_v    k FP64: ||v_q - Y Tv(:, q)||, evaluated from the explicit
+ *            residual (no cancellation).
+ *   workspace at least rbd_project_workspace_size() bytes.
+ *
+ * 1 <= d <= RBD_MAX_D, m >= 1, k >= 1.  Returns RBD_OK, RBD_EINVAL,
+ * RBD_EWORKSPACE or RBD_EDEVICE.
+ */
+int rbd_project(const double* Y, int64_t ldy, int64_t m, int32_t d,
+                const void* V, rbd_dtype vt, int64_t k, int64_t ldv,
+                double* Tv, double* err_v,
+                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Human-readable text for a return or status code (static storage). */
+const char* rbd_status_string(int code);
+
+/* Library version string, e.g. "rbd-gfx950 0.1". */
+const char* rbd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBD_H_ */

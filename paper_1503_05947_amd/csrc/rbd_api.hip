@@ -1,0 +1,368 @@
+// Host side of the RBD library: argument validation, workspace layout,
+// launch plans and the C ABI declared in include/rbd.h.
+//
+// rbd_fit enqueues the whole greedy loop on the caller's stream without ever
+// waiting for the device: for step s = 0 .. D-1 it launches the six kernels of
+// one step with d = s (the device keeps the real d, and every kernel returns
+// at once after the stop flag is set).  The host therefore knows an upper
+// bound of d for each launch and sizes register tiles (KC) from it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "../../include/rbd.h"
+#include "rbd_kernels.h"
+
+namespace {
+
+using namespace rbd;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int elem_bytes(rbd_dtype t) {
+    switch (t) {
+        case RBD_F32: return 4;
+        case RBD_BF16: return 2;
+        case RBD_F16: return 2;
+        case RBD_F64: return 8;
+    }
+    return 0;
+}
+int vec_elems(rbd_dtype t) { return 16 / elem_bytes(t); }
+
+struct FitPlan {
+    int64_t m = 0, n = 0;
+    int D = 0, d_max = 0;
+    rbd_dtype xt = RBD_F32;
+    // X-scan
+    int sc_tpb = 256, sc_tiles = 1, sc_rows = 0, sc_S = 0;
+    // update (combine partials, downdate, argmax)
+    int up_ncb = 0, up_SG = 1;
+    // Gram-Schmidt passes
+    int cg_rows = 0, cg_S = 0, cg_group = 32, cg_ngroups = 0;
+    // exact residual evaluation
+    int rc_rows = 0, rc_S = 0, rc_grid = 0, rf_grid = 0;
+    int ntickets = 0;
+    // workspace offsets (bytes)
+    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_part,
+        o_l2, o_rpart, total;
+};
+
+bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P) {
+    if (m < 1 || n < 1 || d_max < 1) return false;
+    if (elem_bytes(xt) == 0) return false;
+    if (n >= (int64_t)INT32_MAX || m >= ((int64_t)1 << 40)) return false;
+    P->m = m;
+    P->n = n;
+    P->xt = xt;
+    P->d_max = d_max;
+    P->D = (int)std::min<int64_t>(d_max, std::min(m, n));
+    if (P->D > RBD_MAX_D) return false;
+
+    // X-scan: 16-byte loads, 64..256 threads per column tile, ~2048 workgroups
+    const int N = vec_elems(xt);
+    const int64_t nvec = cdiv(n, N);
+    P->sc_tpb = nvec >= 256 ? 256 : (nvec >= 128 ? 128 : 64);
+    P->sc_tiles = (int)cdiv(nvec, P->sc_tpb);
+    int64_t rows = cdiv(m * P->sc_tiles, 2048);
+    rows = std::max<int64_t>(16, std::min<int64_t>(rows, 4096));
+    P->sc_rows = (int)rows;
+    P->sc_S = (int)cdiv(m, rows);
+
+    P->up_ncb = (int)cdiv(n, 256);
+    P->up_SG = (int)std::max<int64_t>(1, std::min<int64_t>(64, cdiv(P->sc_S, 16)));
+
+    // Gram-Schmidt: 4 waves per block, ~2048 blocks, rows a multiple of 16
+    int64_t crow = cdiv(m, 2048);
+    crow = std::max<int64_t>(16, cdiv(crow, 16) * 16);
+    P->cg_rows = (int)crow;
+    P->cg_S = (int)cdiv(m, crow);
+    P->cg_group = 32;
+    P->cg_ngroups = (int)cdiv(P->cg_S, P->cg_group);
+
+    // exact residuals: at most 64 row slabs of a multiple of 64 rows
+    int64_t rrow = std::max<int64_t>(64, cdiv(cdiv(m, 64), 64) * 64);
+    P->rc_rows = (int)std::min<int64_t>(rrow, INT32_MAX / 2);
+    P->rc_S = (int)cdiv(m, rrow);
+    P->rc_grid = (int)std::min<int64_t>(2048, cdiv(n, 64) * P->rc_S);
+    P->rf_grid = (int)cdiv(n, 256);
+
+    P->ntickets = (int)std::max<int64_t>(P->up_ncb + 1, P->cg_ngroups + 1) + 8;
+
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    P->o_state = take(sizeof(State));
+    P->o_tickets = take(sizeof(unsigned) * P->ntickets);
+    P->o_e2 = take(8 * n);
+    P->o_base2 = take(8 * n);
+    P->o_flist = take(4 * n);
+    P->o_bres_v = take(8 * P->up_ncb);
+    P->o_bres_i = take(8 * P->up_ncb);
+    P->o_v1 = take(8 * m);
+    P->o_v2 = take(8 * m);
+    P->o_h2 = take(8 * (size_t)RBD_MAX_D);
+    P->o_nu2 = take(8);
+    const size_t part_elems = std::max<size_t>((size_t)P->sc_S * n, (size_t)P->cg_S * std::max(P->D, 1));
+    P->o_part = take(8 * part_elems);
+    const size_t l2_elems =
+        std::max<size_t>((size_t)P->up_SG * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
+    P->o_l2 = take(8 * l2_elems);
+    P->o_rpart = take(8 * (size_t)P->rc_S * n);
+    P->total = o;
+    return true;
+}
+
+int kc_for(int d) {
+    const int need = std::max(1, (d + kWave - 1) / kWave);
+    int kc = 1;
+    while (kc < need) kc <<= 1;
+    return kc;
+}
+
+#define RBD_LAUNCH_CHECK()                                   \
+    do {                                                     \
+        if (hipGetLastError() != hipSuccess) return RBD_EDEVICE; \
+    } while (0)
+
+template <typename Tx, int KC>
+void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, const double* T, State* st,
+                 int d, double* v1, double* part, double* l2, unsigned* tickets, double* h2,
+                 hipStream_t s) {
+    cgs1_kernel<Tx, KC, 4><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, v1, part,
+                                                   std::max(P.D, 1), l2, P.cg_group, tickets, h2);
+}
+
+template <int KC>
+void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
+                 double* v2, double* part, double* l2, unsigned* tickets, double* nu2, hipStream_t s) {
+    cgs2_kernel<KC, 4><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part, l2,
+                                               P.cg_group, tickets, nu2);
+}
+
+template <typename Tx>
+int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, int64_t start, double* Y,
+              double* T, int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
+              int32_t* stop_reason, char* ws, hipStream_t s) {
+    State* st = reinterpret_cast<State*>(ws + P.o_state);
+    unsigned* tickets = reinterpret_cast<unsigned*>(ws + P.o_tickets);
+    double* e2 = reinterpret_cast<double*>(ws + P.o_e2);
+    double* base2 = reinterpret_cast<double*>(ws + P.o_base2);
+    int* flist = reinterpret_cast<int*>(ws + P.o_flist);
+    double* bres_v = reinterpret_cast<double*>(ws + P.o_bres_v);
+    int64_t* bres_i = reinterpret_cast<int64_t*>(ws + P.o_bres_i);
+    double* v1 = reinterpret_cast<double*>(ws + P.o_v1);
+    double* v2 = reinterpret_cast<double*>(ws + P.o_v2);
+    double* h2 = reinterpret_cast<double*>(ws + P.o_h2);
+    double* nu2 = reinterpret_cast<double*>(ws + P.o_nu2);
+    double* part = reinterpret_cast<double*>(ws + P.o_part);
+    double* l2 = reinterpret_cast<double*>(ws + P.o_l2);
+    double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
+
+    const int N = Ld<Tx>::N;
+    const int vec_ok = (ldx % N == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    const bool nt = (double)P.m * (double)ldx * sizeof(Tx) > 512.0 * 1024 * 1024;
+    const dim3 sc_grid(P.sc_tiles, P.sc_S);
+    const size_t sc_lds = sizeof(double) * P.sc_rows;
+    const dim3 up_grid(P.up_ncb, P.up_SG);
+
+    init_state_kernel<<<1, 256, 0, s>>>(st, tickets, P.ntickets, P.D, flist);
+    RBD_LAUNCH_CHECK();
+    // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
+    xscan_kernel<Tx, kScanSqr, 4, false><<<sc_grid, P.sc_tpb, 0, s>>>(X, ldx, P.m, P.n, nullptr, st, Y, P.d_max, 0,
+                                                                      P.sc_rows, part, vec_ok);
+    RBD_LAUNCH_CHECK();
+    update_kernel<kInit><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, 0, l2, P.up_SG, tickets, e2, base2, T, P.n,
+                                                 flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+    RBD_LAUNCH_CHECK();
+
+    for (int d = 0; d < P.D; ++d) {
+        switch (kc_for(d)) {
+            case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+            case 2: launch_cgs1<Tx, 2>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+            case 4: launch_cgs1<Tx, 4>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+            case 8: launch_cgs1<Tx, 8>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+            default: launch_cgs1<Tx, 16>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        switch (kc_for(d)) {
+            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        if (nt)
+            xscan_kernel<Tx, kScanDot, 4, true><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y, P.d_max,
+                                                                              d, P.sc_rows, part, vec_ok);
+        else
+            xscan_kernel<Tx, kScanDot, 4, false><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y,
+                                                                               P.d_max, d, P.sc_rows, part, vec_ok);
+        RBD_LAUNCH_CHECK();
+        update_kernel<kStep><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, d, l2, P.up_SG, tickets, e2, base2, T,
+                                                     P.n, flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        RBD_LAUNCH_CHECK();
+        resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+                                                    P.rc_rows, P.rc_S, rpart, P.n);
+        RBD_LAUNCH_CHECK();
+        resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, rpart, P.n, P.rc_S, flist, e2, base2, P.n, tickets, pivots,
+                                                      err_hist, d);
+        RBD_LAUNCH_CHECK();
+    }
+    const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
+    const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
+    epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
+                                       stop_reason);
+    RBD_LAUNCH_CHECK();
+    return RBD_OK;
+}
+
+// ---------------------------------------------------------------------------
+struct ProjPlan {
+    int S = 1, rows = 0;
+    int rc_rows = 0, rc_S = 0, rc_grid = 0;
+    size_t o_part, o_rpart, total;
+};
+
+bool make_proj_plan(int64_t m, int32_t d, int64_t k, ProjPlan* P) {
+    if (m < 1 || d < 1 || k < 1 || d > RBD_MAX_D || k >= (int64_t)INT32_MAX) return false;
+    P->S = (int)std::max<int64_t>(1, std::min<int64_t>(32, cdiv(m, 8192)));
+    P->rows = (int)cdiv(m, P->S);
+    P->rows = (int)(cdiv(P->rows, 16) * 16);
+    P->S = (int)cdiv(m, P->rows);
+    int64_t rrow = std::max<int64_t>(64, cdiv(cdiv(m, 64), 64) * 64);
+    P->rc_rows = (int)rrow;
+    P->rc_S = (int)cdiv(m, rrow);
+    P->rc_grid = (int)std::min<int64_t>(2048, cdiv(k, 64) * P->rc_S);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    P->o_part = take(8 * (size_t)P->S * d * k);
+    P->o_rpart = take(8 * (size_t)P->rc_S * k);
+    P->total = o;
+    return true;
+}
+
+template <typename Tv>
+int project_typed(const ProjPlan& P, const double* Y, int64_t ldy, int64_t m, int d, const Tv* V, int64_t k,
+                  int64_t ldv, double* Tv_out, double* err_v, char* ws, hipStream_t s) {
+    double* part = reinterpret_cast<double*>(ws + P.o_part);
+    double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
+    const dim3 g((unsigned)cdiv(d, 64), (unsigned)cdiv(k, 64), (unsigned)P.S);
+    gemm_tn_partial_kernel<Tv><<<g, 256, 0, s>>>(Y, ldy, m, d, V, ldv, k, P.rows, part);
+    RBD_LAUNCH_CHECK();
+    const int64_t len = (int64_t)d * k;
+    sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(len, 256)), 256, 0, s>>>(part, P.S, len, Tv_out, 0);
+    RBD_LAUNCH_CHECK();
+    resid_kernel<Tv><<<P.rc_grid, 256, 0, s>>>(V, ldv, m, Y, ldy, d, Tv_out, k, nullptr, nullptr, (int)k, P.rc_rows,
+                                               P.rc_S, rpart, k);
+    RBD_LAUNCH_CHECK();
+    sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(k, 256)), 256, 0, s>>>(rpart, P.rc_S, k, err_v, 1);
+    RBD_LAUNCH_CHECK();
+    return RBD_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int rbd_fit_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes) {
+    if (!bytes) return RBD_EINVAL;
+    FitPlan P;
+    if (!make_fit_plan(m, n, d_max, xt, &P)) return RBD_EINVAL;
+    *bytes = P.total;
+    return RBD_OK;
+}
+
+int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
+            int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+            int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace, size_t workspace_bytes,
+            void* stream) {
+    FitPlan P;
+    if (!make_fit_plan(m, n, d_max, xt, &P)) return RBD_EINVAL;
+    if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status || !workspace) return RBD_EINVAL;
+    if (ldx < n) return RBD_EINVAL;
+    if (!(tol >= 0.0) || tol == HUGE_VAL) return RBD_EINVAL;
+    if (mode != RBD_TOL_ABS && mode != RBD_TOL_REL) return RBD_EINVAL;
+    if (start >= n) return RBD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return RBD_EINVAL;
+    if (workspace_bytes < P.total) return RBD_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    const int rel = (mode == RBD_TOL_REL);
+    switch (xt) {
+        case RBD_F32:
+            return fit_typed<float>(P, static_cast<const float*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
+                                    err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_F64:
+            return fit_typed<double>(P, static_cast<const double*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
+                                     err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_BF16:
+            return fit_typed<bf16_t>(P, static_cast<const bf16_t*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
+                                     err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_F16:
+            return fit_typed<f16_t>(P, static_cast<const f16_t*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
+                                    err_hist, d_out, status, stop_reason, ws, s);
+    }
+    return RBD_EINVAL;
+}
+
+int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes) {
+    if (!bytes || elem_bytes(vt) == 0) return RBD_EINVAL;
+    ProjPlan P;
+    if (!make_proj_plan(m, d, k, &P)) return RBD_EINVAL;
+    *bytes = P.total;
+    return RBD_OK;
+}
+
+int rbd_project(const double* Y, int64_t ldy, int64_t m, int32_t d, const void* V, rbd_dtype vt, int64_t k,
+                int64_t ldv, double* Tv, double* err_v, void* workspace, size_t workspace_bytes, void* stream) {
+    ProjPlan P;
+    if (elem_bytes(vt) == 0 || !make_proj_plan(m, d, k, &P)) return RBD_EINVAL;
+    if (!Y || !V || !Tv || !err_v || !workspace) return RBD_EINVAL;
+    if (ldy < d || ldv < k) return RBD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return RBD_EINVAL;
+    if (workspace_bytes < P.total) return RBD_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    switch (vt) {
+        case RBD_F32:
+            return project_typed<float>(P, Y, ldy, m, d, static_cast<const float*>(V), k, ldv, Tv, err_v, ws, s);
+        case RBD_F64:
+            return project_typed<double>(P, Y, ldy, m, d, static_cast<const double*>(V), k, ldv, Tv, err_v, ws, s);
+        case RBD_BF16:
+            return project_typed<bf16_t>(P, Y, ldy, m, d, static_cast<const bf16_t*>(V), k, ldv, Tv, err_v, ws, s);
+        case RBD_F16:
+            return project_typed<f16_t>(P, Y, ldy, m, d, static_cast<const f16_t*>(V), k, ldv, Tv, err_v, ws, s);
+    }
+    return RBD_EINVAL;
+}
+
+const char* rbd_status_string(int code) {
+    switch (code) {
+        case RBD_OK: return "ok";
+        case RBD_EINVAL: return "invalid argument";
+        case RBD_ENONFINITE: return "input holds a non-finite value";
+        case RBD_EWORKSPACE: return "workspace too small";
+        case RBD_EDEVICE: return "HIP launch or runtime error";
+    }
+    return "unknown status";
+}
+
+const char* rbd_version(void) { return "rbd-gfx950 0.1"; }
+
+}  // extern "C"

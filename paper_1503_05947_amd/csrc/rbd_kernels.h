@@ -1,0 +1,569 @@
+// Kernels of the greedy loop of Reduced Basis Decomposition (Algorithm 1,
+// section 3.1) with A = I (eq. (3)).  One greedy step is six stream-ordered
+// kernels; every kernel reads the device-side stop flag first, so steps past
+// the end of the loop cost one empty launch each and the host never waits.
+//
+//   cgs1   v1 = x_p - Y h1 with h1 = T(0:d, p)   (first Gram-Schmidt pass;
+//          h1 = Y' x_p is already a column of T), fused with the partial
+//          sums of h2 = Y' v1
+//   cgs2   v2 = v1 - Y h2 (second pass), nu = ||v2||, step 2.2's break test
+//   xscan  xi = v2 / nu written to Y(:, d); T(d, :) partials = xi' X per row slab
+//   update T(d, :) = sum of partials; e_j^2 -= T(d, j)^2; queue columns whose
+//          downdated error fell below kappa * (last exact value); argmax
+//   resid  exact ||x_j - Y T(:, j)||^2 for queued columns (a small FP64 GEMM)
+//   resid_finish  store exact values, argmax, stop test of step 2.4
+#pragma once
+
+#include "rbd_device.h"
+
+namespace rbd {
+
+constexpr int kStopError = 4;           // internal: non-finite input
+constexpr double kRefresh = 0x1p-20;    // kappa: re-evaluate when e^2 < kappa * base^2
+
+enum { kScanDot = 0, kScanSqr = 1 };
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void finish_step(State* st, int d, double vmax, int64_t imax,
+                                            int64_t* pivots, double* err_hist) {
+    const double E = sqrt(vmax);
+    pivots[d] = st->p;
+    err_hist[d + 1] = E;
+    st->d = d + 1;
+    st->p = (int)imax;
+    if (E <= st->tau) st->stop = RBD_STOP_TOL;
+    else if (d + 1 >= st->D) st->stop = RBD_STOP_DMAX;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, int D, int* flist) {
+    for (int i = threadIdx.x; i < ntickets; i += blockDim.x) tickets[i] = 0u;
+    if (threadIdx.x == 0) {
+        st->d = 0; st->p = 0; st->stop = 0; st->status = RBD_OK; st->nflag = 0; st->D = D;
+        st->nonfinite = 0; st->pad0 = 0;
+        st->tau = 0.0; st->E0 = 0.0; st->nu = 0.0; st->inv_nu = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// X-scan: per row slab, acc_j = sum_i w_i x_ij (DOT, w = xi) or sum_i x_ij^2 (SQR).
+// Grid (column tiles, row slabs); each thread owns Ld<Tx>::N adjacent columns
+// and streams the slab's rows with 16-byte loads, U rows in flight.
+// ---------------------------------------------------------------------------
+template <typename Tx, int MODE, int U, bool NT>
+__global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                     int64_t n, const double* __restrict__ v2,
+                                                     State* __restrict__ st, double* __restrict__ Y,
+                                                     int64_t ldy, int dcol, int rows_per_slab,
+                                                     double* __restrict__ part, int vec_ok) {
+    if (MODE == kScanDot && st->stop) return;
+    using L = Ld<Tx>;
+    constexpr int N = L::N;
+    extern __shared__ double xi_s[];
+    const int tile = blockIdx.x, slab = blockIdx.y;
+    const int64_t r0 = (int64_t)slab * rows_per_slab;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_slab);
+    const int nr = (int)(r1 - r0);
+    if (MODE == kScanDot) {
+        const double inv = st->inv_nu;
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+            const double xi = v2[r0 + r] * inv;
+            xi_s[r] = xi;
+            if (tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
+        }
+        __syncthreads();
+    }
+    const int64_t c0 = ((int64_t)tile * blockDim.x + threadIdx.x) * N;
+    if (c0 >= n) return;
+    double acc[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) acc[q] = 0.0;
+    const Tx* p = X + r0 * ldx + c0;
+    if (vec_ok && c0 + N <= n) {
+        using R = typename L::raw;
+        int r = 0;
+        for (; r + U <= nr; r += U) {
+            R raw[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const R* a = reinterpret_cast<const R*>(p + (int64_t)(r + u) * ldx);
+                raw[u] = NT ? __builtin_nontemporal_load(a) : *a;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double x[N];
+                L::cvt(raw[u], x);
+                if (MODE == kScanDot) {
+                    const double w = xi_s[r + u];
+#pragma unroll
+                    for (int q = 0; q < N; ++q) acc[q] = fma(w, x[q], acc[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < N; ++q) acc[q] = fma(x[q], x[q], acc[q]);
+                }
+            }
+        }
+        for (; r < nr; ++r) {
+            double x[N];
+            L::cvt(*reinterpret_cast<const R*>(p + (int64_t)r * ldx), x);
+            const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) acc[q] = (MODE == kScanDot) ? fma(w, x[q], acc[q]) : fma(x[q], x[q], acc[q]);
+        }
+    } else {
+        const int nc = (int)min((int64_t)N, n - c0);
+        for (int r = 0; r < nr; ++r) {
+            const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
+            for (int q = 0; q < nc; ++q) {
+                const double x = L::one(p + (int64_t)r * ldx + q);
+                acc[q] = (MODE == kScanDot) ? fma(w, x, acc[q]) : fma(x, x, acc[q]);
+            }
+        }
+    }
+    double* out = part + (int64_t)slab * n + c0;
+    const int nc = (int)min((int64_t)N, n - c0);
+    for (int q = 0; q < nc; ++q) out[q] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// update: combine the scan partials of each column (two levels, fixed order),
+// then either initialise the errors (INIT) or downdate them (STEP), and take
+// the lowest-index argmax.  Grid (column blocks of 256, slab groups SG).
+// ---------------------------------------------------------------------------
+enum { kInit = 0, kStep = 1 };
+
+template <int MODE>
+__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ part, int S, int64_t n,
+                                                      State* __restrict__ st, int d, double* __restrict__ l2,
+                                                      int SG, unsigned* __restrict__ tickets,
+                                                      double* __restrict__ e2, double* __restrict__ base2,
+                                                      double* __restrict__ T, int64_t ldt, int* __restrict__ flist,
+                                                      double* __restrict__ bres_v, int64_t* __restrict__ bres_i,
+                                                      int64_t* __restrict__ pivots, double* __restrict__ err_hist,
+                                                      int64_t start, double tol, int rel) {
+    if (MODE == kStep && st->stop) return;
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    const int cb = blockIdx.x, g = blockIdx.y, ncb = gridDim.x;
+    const int64_t j = (int64_t)cb * blockDim.x + threadIdx.x;
+    const int s0 = (int)((int64_t)g * S / SG), s1 = (int)((int64_t)(g + 1) * S / SG);
+    if (j < n) {
+        double s = 0.0;
+        for (int q = s0; q < s1; ++q) s += part[(int64_t)q * n + j];
+        l2[(int64_t)g * n + j] = s;
+    }
+    if (!last_to_arrive(&tickets[cb], (unsigned)SG)) return;
+
+    double best = -1.0;
+    int64_t bi = INT64_MAX;
+    if (j < n) {
+        double t = 0.0;
+        for (int q = 0; q < SG; ++q) t += l2[(int64_t)q * n + j];
+        double e;
+        if (MODE == kInit) {
+            e = t;
+            e2[j] = e;
+            base2[j] = e;
+            if (!isfinite(e)) atomicOr(&st->nonfinite, 1);
+        } else {
+            T[(int64_t)d * ldt + j] = t;
+            e = e2[j] - t * t;
+            if (!(e > 0.0)) e = 0.0;
+            double b = base2[j];
+            if (j == (int64_t)st->p) {
+                e = 0.0;
+                b = 0.0;
+                base2[j] = 0.0;
+            }
+            e2[j] = e;
+            if (e < kRefresh * b) {
+                const int pos = atomicAdd(&st->nflag, 1);
+                flist[pos] = (int)j;
+            }
+        }
+        if (e == e) { best = e; bi = j; }
+    }
+    block_argmax(best, bi, sv, si);
+    if (threadIdx.x == 0) { bres_v[cb] = best; bres_i[cb] = bi; }
+    if (!last_to_arrive(&tickets[ncb], (unsigned)ncb)) return;
+    if (threadIdx.x == 0) {
+        double v = -1.0;
+        int64_t i = INT64_MAX;
+        for (int c = 0; c < ncb; ++c) argmax_merge(v, i, bres_v[c], bres_i[c]);
+        if (MODE == kInit) {
+            if (st->nonfinite) {
+                st->status = RBD_ENONFINITE;
+                st->stop = kStopError;
+                st->E0 = NAN;
+                err_hist[0] = NAN;
+            } else {
+                const double E0 = sqrt(v);
+                st->E0 = E0;
+                st->tau = rel ? tol * E0 : tol;
+                st->p = start >= 0 ? (int)start : (int)i;
+                err_hist[0] = E0;
+            }
+        } else if (st->nflag == 0) {
+            finish_step(st, d, v, i, pivots, err_hist);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cgs1: v1 = x_p - Y(:, 0:d) h1, h1 = T(0:d, p); partial h2 = Y' v1 per block.
+// One wave per row of Y (lanes run along k), RU rows in flight per wave; the
+// wave keeps its share of h2 in registers, so Y is read once.
+// ---------------------------------------------------------------------------
+template <typename Tx, int KC, int RU>
+__global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                    const double* __restrict__ Y, int64_t ldy,
+                                                    const double* __restrict__ T, int64_t ldt,
+                                                    State* __restrict__ st, int d, int rows_per_blk,
+                                                    double* __restrict__ v1, double* __restrict__ part,
+                                                    int64_t ldp, double* __restrict__ l2, int group,
+                                                    unsigned* __restrict__ tickets, double* __restrict__ h2) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    __shared__ double accs[KW];
+    const int p = st->p;
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? T[(int64_t)k * ldt + p] : 0.0;
+        accs[k] = 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+        double xv[RU];
+        double dot[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+            xv[u] = ok ? Ld<Tx>::one(X + r * ldx + p) : 0.0;
+            dot[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
+            dot[u] = wave_sum(dot[u]);
+            const int64_t r = rb + u;
+            const double v = xv[u] - dot[u];
+            if (r < r1) {
+                if (lane == 0) v1[r] = v;
+#pragma unroll
+                for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
+            }
+        }
+    }
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (w == q) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += acc[c];
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
+    grid_reduce_rows(part, ldp, gridDim.x, d, l2, group, tickets, h2, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// cgs2: v2 = v1 - Y(:, 0:d) h2, nu = ||v2||, and step 2.2's break test.
+// ---------------------------------------------------------------------------
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                    State* __restrict__ st, int d, int rows_per_blk,
+                                                    const double* __restrict__ v1, const double* __restrict__ h2,
+                                                    double* __restrict__ v2, double* __restrict__ part,
+                                                    double* __restrict__ l2, int group,
+                                                    unsigned* __restrict__ tickets, double* __restrict__ nu2) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    __shared__ double sred[4];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? h2[k] : 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double nacc = 0.0;
+    for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+        double vv[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+            vv[u] = ok ? v1[r] : 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            double dot = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) dot = fma(y[u][c], hs[lane + kWave * c], dot);
+            dot = wave_sum(dot);
+            const int64_t r = rb + u;
+            const double v = vv[u] - dot;
+            if (r < r1 && lane == 0) {
+                v2[r] = v;
+                nacc = fma(v, v, nacc);
+            }
+        }
+    }
+    const double s = block_sum(lane == 0 ? nacc : 0.0, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (grid_reduce_rows(part, 1, gridDim.x, 1, l2, group, tickets, nu2, blockIdx.x)) {
+        if (threadIdx.x == 0) {
+            const double nu = sqrt(nu2[0]);
+            st->nu = nu;
+            if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
+            else st->inv_nu = 1.0 / nu;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// resid: partial squared residual norms of selected columns,
+//   part[s * ldp + jj] = sum_{i in slab s} (X[i, c] - sum_{k<K} Y[i, k] C[k, c])^2,
+// c = J ? J[jj] : jj, for jj < count.  64 x 64 output tiles, FP64 FMA.
+// Work items (column group, slab) are strided over a fixed grid.
+// ---------------------------------------------------------------------------
+template <typename Tx>
+__global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                     const double* __restrict__ Y, int64_t ldy, int K,
+                                                     const double* __restrict__ C, int64_t ldc,
+                                                     const int* __restrict__ J, const int* __restrict__ count_dev,
+                                                     int count_host, int rows_per_slab, int nslab,
+                                                     double* __restrict__ part, int64_t ldp) {
+    const int cnt = count_dev ? *count_dev : count_host;
+    if (cnt == 0) return;
+    __shared__ double Ys[64][17];
+    __shared__ double Cs[16][65];
+    __shared__ double red[16][65];
+    __shared__ int cols[64];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int njg = (cnt + 63) / 64;
+    const int nwork = njg * nslab;
+    for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int jg = wk % njg, s = wk / njg;
+        __syncthreads();
+        if (tid < 64) {
+            const int jj = jg * 64 + tid;
+            cols[tid] = (jj < cnt) ? (J ? J[jj] : jj) : -1;
+        }
+        __syncthreads();
+        const int64_t rbeg = (int64_t)s * rows_per_slab;
+        const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
+        double rs[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t row0 = rbeg; row0 < rend; row0 += 64) {
+            double acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+            for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = tid + 256 * q;
+                    const int rr = e >> 4, kk = e & 15;
+                    const int64_t row = row0 + rr;
+                    const int k = k0 + kk;
+                    Ys[rr][kk] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = tid + 256 * q;
+                    const int kk = e >> 6, cc = e & 63;
+                    const int k = k0 + kk;
+                    const int col = cols[cc];
+                    Cs[kk][cc] = (k < K && col >= 0) ? C[(int64_t)k * ldc + col] : 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    double yv[4], cv[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) yv[a] = Ys[ty + 16 * a][kk];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) cv[b] = Cs[kk][tx + 16 * b];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], cv[b], acc[a][b]);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int64_t row = row0 + ty + 16 * a;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int col = cols[tx + 16 * b];
+                    if (row < rend && col >= 0) {
+                        const double r = Ld<Tx>::one(X + row * ldx + col) - acc[a][b];
+                        rs[b] = fma(r, r, rs[b]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) red[ty][tx + 16 * b] = rs[b];
+        __syncthreads();
+        if (tid < 64) {
+            double sum = 0.0;
+            for (int t = 0; t < 16; ++t) sum += red[t][tid];
+            const int jj = jg * 64 + tid;
+            if (jj < cnt) part[(int64_t)s * ldp + jj] = sum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// resid_finish: exact errors replace the downdated ones, then argmax + stop.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void resid_finish_kernel(State* __restrict__ st, const double* __restrict__ part,
+                                                            int64_t ldp, int nslab, const int* __restrict__ J,
+                                                            double* __restrict__ e2, double* __restrict__ base2,
+                                                            int64_t n, unsigned* __restrict__ tickets,
+                                                            int64_t* __restrict__ pivots,
+                                                            double* __restrict__ err_hist, int d) {
+    const int cnt = st->nflag;
+    if (cnt == 0) return;
+    __shared__ double sv[4];
+    __shared__ int64_t si[4];
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj < cnt) {
+        double s = 0.0;
+        for (int q = 0; q < nslab; ++q) s += part[(int64_t)q * ldp + jj];
+        const int j = J[jj];
+        e2[j] = s;
+        base2[j] = s;
+    }
+    if (!last_to_arrive(&tickets[0], gridDim.x)) return;
+    double v = -1.0;
+    int64_t i = INT64_MAX;
+    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) argmax_merge(v, i, e2[j], j);
+    block_argmax(v, i, sv, si);
+    if (threadIdx.x == 0) {
+        finish_step(st, d, v, i, pivots, err_hist);
+        st->nflag = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// epilogue: col_err = sqrt(e^2), zero unused columns/rows, publish d and status.
+// ---------------------------------------------------------------------------
+__global__ void epilogue_kernel(const State* __restrict__ st, const double* __restrict__ e2,
+                                double* __restrict__ col_err, int64_t n, double* __restrict__ Y, int64_t m,
+                                int d_max, double* __restrict__ T, int64_t* __restrict__ pivots,
+                                double* __restrict__ err_hist, int32_t* d_out, int32_t* status,
+                                int32_t* stop_reason) {
+    const int d = st->d;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = gid; j < n; j += stride) col_err[j] = sqrt(e2[j]);
+    if (d < d_max) {
+        for (int64_t i = gid; i < m; i += stride)
+            for (int k = d; k < d_max; ++k) Y[i * d_max + k] = 0.0;
+        const int64_t tot = (int64_t)(d_max - d) * n;
+        for (int64_t e = gid; e < tot; e += stride) T[(int64_t)d * n + e] = 0.0;
+    }
+    for (int64_t k = gid; k < d_max; k += stride)
+        if (k >= d) pivots[k] = -1;
+    for (int64_t k = gid; k <= d_max; k += stride)
+        if (k > d) err_hist[k] = 0.0;
+    if (gid == 0) {
+        *d_out = d;
+        *status = st->status;
+        if (stop_reason) *stop_reason = (st->stop == kStopError) ? 0 : st->stop;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// projection: C = Y' V over row slabs (partials), then a fixed-order sum.
+// ---------------------------------------------------------------------------
+template <typename Tv>
+__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(const double* __restrict__ Y, int64_t ldy,
+                                                               int64_t m, int d, const Tv* __restrict__ V,
+                                                               int64_t ldv, int64_t k, int rows_per_slab,
+                                                               double* __restrict__ part) {
+    __shared__ double Ys[16][65];
+    __shared__ double Vs[16][65];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int a0 = blockIdx.x * 64;
+    const int64_t q0 = (int64_t)blockIdx.y * 64;
+    const int s = blockIdx.z;
+    const int64_t rbeg = (int64_t)s * rows_per_slab;
+    const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int64_t row0 = rbeg; row0 < rend; row0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int rr = e >> 6, cc = e & 63;
+            const int64_t row = row0 + rr;
+            const int a = a0 + cc;
+            const int64_t qq = q0 + cc;
+            Ys[rr][cc] = (row < rend && a < d) ? Y[row * ldy + a] : 0.0;
+            Vs[rr][cc] = (row < rend && qq < k) ? Ld<Tv>::one(V + row * ldv + qq) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+            double yv[4], vv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) yv[a] = Ys[rr][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) vv[b] = Vs[rr][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], vv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    double* out = part + (int64_t)s * d * k;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int aa = a0 + ty + 16 * a;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t qq = q0 + tx + 16 * b;
+            if (aa < d && qq < k) out[(int64_t)aa * k + qq] = acc[a][b];
+        }
+    }
+}
+
+// out[e] = f(sum_{s < S} part[s * len + e]) with f = identity or sqrt.
+__global__ void sum_rows_kernel(const double* __restrict__ part, int S, int64_t len, double* __restrict__ out,
+                                int take_sqrt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < S; ++q) s += part[(int64_t)q * len + e];
+        out[e] = take_sqrt ? sqrt(s) : s;
+    }
+}
+
+}  // namespace rbd

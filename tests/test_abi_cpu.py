@@ -1,0 +1,126 @@
+"""CPU-side checks of the C-ABI library: it loads without a GPU, exports every
+function include/rbd.h declares, sizes workspaces, and rejects bad arguments
+before any device call.  Also checks the separation between the product
+package and the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1503_05947_amd import _build, _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        _build.build_library()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rbd_fit", "rbd_fit_workspace_size", "rbd_project", "rbd_project_workspace_size",
+                 "rbd_status_string"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1503_05947_amd import _lib
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version_and_status_strings(lib):
+    assert lib.rbd_version().decode().startswith("rbd-gfx950")
+    for code in (0, -1, -2, -3, -4):
+        assert lib.rbd_status_string(code)
+    assert lib.rbd_status_string(123) == b"unknown status"
+
+
+def test_workspace_size_queries(lib):
+    from paper_1503_05947_amd import _lib
+    small = _lib.fit_workspace_size(512, 256, 64, _lib.RBD_F32)
+    big = _lib.fit_workspace_size(1 << 20, 4096, 512, _lib.RBD_F32)
+    assert 0 < small < big < (1 << 30)
+    assert _lib.fit_workspace_size(512, 256, 64, _lib.RBD_BF16) > 0
+    assert _lib.project_workspace_size(1000, 20, 7, _lib.RBD_F64) > 0
+    out = ctypes.c_size_t(0)
+    assert lib.rbd_fit_workspace_size(0, 10, 5, 0, ctypes.byref(out)) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_workspace_size(10, 10, 0, 0, ctypes.byref(out)) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_workspace_size(10, 10, 5, 9, ctypes.byref(out)) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_workspace_size(5000, 5000, 2000, 0, ctypes.byref(out)) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_workspace_size(10, 10, 5, 0, None) == _lib.RBD_EINVAL
+
+
+def test_fit_argument_validation_without_device(lib):
+    from paper_1503_05947_amd import _lib
+    fake = ctypes.c_void_p(4096)           # never dereferenced: validation fails first
+    ws = ctypes.c_void_p(1 << 20)
+
+    def call(**kw):
+        a = dict(X=fake, xt=0, m=10, n=10, ldx=10, tol=0.0, mode=0, d_max=5, start=-1, Y=fake, T=fake,
+                 piv=fake, ce=fake, eh=fake, dout=fake, st=fake, sr=None, ws=ws, wsb=0, stream=None)
+        a.update(kw)
+        return lib.rbd_fit(a["X"], a["xt"], a["m"], a["n"], a["ldx"], a["tol"], a["mode"], a["d_max"],
+                           a["start"], a["Y"], a["T"], a["piv"], a["ce"], a["eh"], a["dout"], a["st"], a["sr"],
+                           a["ws"], a["wsb"], a["stream"])
+
+    assert call(X=None) == _lib.RBD_EINVAL
+    assert call(ldx=9) == _lib.RBD_EINVAL
+    assert call(tol=-1.0) == _lib.RBD_EINVAL
+    assert call(tol=float("nan")) == _lib.RBD_EINVAL
+    assert call(tol=float("inf")) == _lib.RBD_EINVAL
+    assert call(mode=5) == _lib.RBD_EINVAL
+    assert call(start=10) == _lib.RBD_EINVAL
+    assert call(d_max=0) == _lib.RBD_EINVAL
+    assert call(ws=ctypes.c_void_p((1 << 20) + 8)) == _lib.RBD_EINVAL     # misaligned workspace
+    assert call(wsb=16) == _lib.RBD_EWORKSPACE
+
+
+def test_project_argument_validation_without_device(lib):
+    from paper_1503_05947_amd import _lib
+    fake = ctypes.c_void_p(4096)
+    rc = lib.rbd_project(fake, 3, 10, 5, fake, 0, 4, 4, fake, fake, ctypes.c_void_p(1 << 20), 1 << 30, None)
+    assert rc == _lib.RBD_EINVAL     # ldy < d
+    rc = lib.rbd_project(fake, 5, 10, 5, fake, 0, 4, 4, fake, fake, ctypes.c_void_p(1 << 20), 8, None)
+    assert rc == _lib.RBD_EWORKSPACE
+    rc = lib.rbd_project(fake, 5, 10, 0, fake, 0, 4, 4, fake, fake, ctypes.c_void_p(1 << 20), 1 << 30, None)
+    assert rc == _lib.RBD_EINVAL
+
+
+def test_product_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1503_05947_amd")
+    for dirpath, _dirs, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text, f"{f} mentions the oracle"
+                assert "import synth" not in text and "from synth" not in text, f
+
+
+def test_oracle_shares_no_code_with_the_product():
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith(".py"):
+            text = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_1503_05947_amd" not in text
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1503_05947_amd import _lib
+    with pytest.raises(_lib.LibraryMissing):
+        _lib._lib_saved = _lib._lib
+        try:
+            _lib._lib = None
+            _lib.load(str(tmp_path / "nope.so"))
+        finally:
+            _lib._lib = _lib._lib_saved
