@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Throughput of the RBD greedy loop on one MI355X.
+
+Workload: the parametric-field snapshot matrix x_j(s) = sum_{k<8} exp(-mu_jk
+|s - c_k|^2) on a 1024 x 1024 grid (m = 1,048,576 rows) with n = 4096
+parameter draws, tol = 0, d_max = 512 (every fit runs all 512 greedy steps).
+One bench step is one complete rbd_fit.  X is resident in HBM before timing.
+
+Reported: greedy steps/s for FP32 storage (``value``), the same for BF16
+storage, the X-scan kernel's achieved bandwidth against the 8 TB/s HBM peak
+(kernel time from HIP events recorded on the fit's stream inside the timed
+region), the BF16-vs-FP32 time to reach equal error against the FP64 field,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+EPS_BOTH = (1e-1, 3e-2, 1e-2, 5e-3)
+EPS_FP32 = (1e-4, 1e-5, 1e-6)
+UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8 + 2.0 ** -24, "f16": 2.0 ** -11, "f64": 2.0 ** -53}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed fits")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed fits")
+    ap.add_argument("--grid", type=int, default=1024, help="field grid g (m = g*g)")
+    ap.add_argument("--n", type=int, default=4096, help="columns (parameter draws)")
+    ap.add_argument("--d-max", type=int, default=512)
+    ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-equal-error", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phases", action="store_true", help="extra profiled fit with a per-phase breakdown")
+    ap.add_argument("--sample-cols", type=int, default=64)
+    return ap.parse_args()
+
+
+def ensure_built():
+    from paper_1503_05947_amd import _build, _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        log("librbd.so missing: building")
+        _build.build_library()
+
+
+def time_fits(rbd, X, d_max, K, W):
+    import torch
+    from paper_1503_05947_amd import _lib
+    bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
+    for _ in range(W):
+        rbd.fit_into(bufs, X, tol=0.0)
+    torch.cuda.synchronize()
+    with _lib.Profiler(phases=("xscan",), max_steps=d_max) as prof:
+        t0 = time.perf_counter()
+        for _ in range(K):
+            rbd.fit_into(bufs, X, tol=0.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    res = bufs.result()
+    return dict(seconds=t1 - t0, fits=K, d=res.d, xscan_ms=prof.avg_ms("xscan"),
+                xscan_launches=prof.launches["xscan"], step_end_ms=list(prof.step_end_ms), bufs=bufs, res=res)
+
+
+def phase_breakdown(rbd, X, d_max):
+    import torch
+    from paper_1503_05947_amd import _lib
+    bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
+    torch.cuda.synchronize()
+    with _lib.Profiler(max_steps=d_max) as prof:
+        rbd.fit_into(bufs, X, tol=0.0)
+    torch.cuda.synchronize()
+    return {p: dict(ms=round(prof.phase_ms[p], 4), launches=prof.launches[p],
+                    avg_us=round(1e3 * prof.avg_ms(p), 3)) for p in _lib.PHASES}
+
+
+# ---------------------------------------------------------------------------
+# equal-error comparison against the FP64 field
+# ---------------------------------------------------------------------------
+def checkpoints(d):
+    pts = list(range(8, min(d, 128) + 1, 8)) + list(range(160, d + 1, 32))
+    if d not in pts:
+        pts.append(d)
+    return sorted(set(p for p in pts if p <= d))
+
+
+def sampled_true_error(Y, T, X64J, J, ds):
+    """max over sampled columns of ||x64_j - Y[:, :d] T[:d, j]|| at each checkpoint d (FP64, host)."""
+    import numpy as np
+    R = X64J.copy()
+    out = []
+    k0 = 0
+    for d in ds:
+        if d > k0:
+            R -= Y[:, k0:d] @ T[k0:d][:, J]
+            k0 = d
+        out.append(float(np.sqrt(np.einsum("ij,ij->j", R, R)).max()))
+    return out
+
+
+def equal_error_report(runs, pf, ncols):
+    import numpy as np
+    import synth
+    g = np.random.default_rng(12345)
+    J = np.sort(g.choice(pf.n, size=min(ncols, pf.n), replace=False))
+    log(f"equal-error: generating {len(J)} FP64 columns on the host")
+    A, B = pf.factors(cols=J)
+    rows = np.arange(pf.m)
+    a, b = rows // pf.grid, rows % pf.grid
+    X64J = A[0][a] * B[0][b]
+    for k in range(1, A.shape[0]):
+        X64J = X64J + A[k][a] * B[k][b]
+    nx64 = np.linalg.norm(X64J, axis=0)
+    report = {"columns_sampled": int(len(J)), "checkpoints": None, "precisions": {}}
+    E0_64_bound = None
+    for name, run in runs.items():
+        res = run["res"]
+        d = res.d
+        ds = checkpoints(d)
+        report["checkpoints"] = ds
+        log(f"equal-error: {name}: copying Y ({res.Y.numel() * 8 / 2**30:.1f} GiB) and evaluating")
+        Y = res.Y.cpu().numpy()
+        T = res.T.cpu().numpy()
+        sampled = sampled_true_error(Y, T, X64J, J, ds)
+        del Y
+        hist = res.err_hist.cpu().numpy()
+        E0 = float(hist[0])                      # max ||x_j^P|| (stored values)
+        u = UNIT_ROUNDOFF[name]
+        # ||x64 - Y t|| <= ||x^P - Y t|| + ||x64 - x^P|| <= E_d + u/(1-u) * max ||x^P||
+        q = u / (1.0 - u) * E0
+        E0_64_bound = E0 / (1.0 + u)             # lower bound of max ||x64_j||
+        cert = [(float(hist[k]) + q) / E0_64_bound for k in range(d + 1)]
+        steps = run["step_end_ms"]
+        entry = {"E0_stored": E0, "sampled_rel_err": [s / nx64.max() for s in sampled],
+                 "certified_rel_err_at_checkpoints": [cert[k] for k in ds], "time_to_eps_ms": {}}
+        for eps in EPS_BOTH + (EPS_FP32 if name == "f32" else ()):
+            dd = next((k for k in range(1, d + 1) if cert[k] <= eps), None)
+            entry["time_to_eps_ms"][f"{eps:g}"] = (
+                None if dd is None else {"d": dd, "ms": round(steps[dd - 1], 3) if dd - 1 < len(steps) else None})
+        report["precisions"][name] = entry
+    if "f32" in report["precisions"] and "bf16" in report["precisions"]:
+        ratio = {}
+        for eps in EPS_BOTH:
+            a32 = report["precisions"]["f32"]["time_to_eps_ms"][f"{eps:g}"]
+            a16 = report["precisions"]["bf16"]["time_to_eps_ms"][f"{eps:g}"]
+            ratio[f"{eps:g}"] = (round(a32["ms"] / a16["ms"], 3)
+                                 if a32 and a16 and a32["ms"] and a16["ms"] else None)
+        report["time_fp32_over_bf16"] = ratio
+    return report
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------
+def cpu_baseline(full_m, grid_sample=256, n=4096, steps=8):
+    import numpy as np
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    pf = synth.parametric_field(0, grid=grid_sample, n=n)
+    X = synth.quantize(pf.full(), "f32")[1]
+    m = X.shape[0]
+    t0 = time.perf_counter()
+    oracle.rbd_fit(X, 0.0, 1)                    # set-up plus one step
+    t1 = time.perf_counter()
+    oracle.rbd_fit(X, 0.0, 1 + steps)
+    t2 = time.perf_counter()
+    per_step = ((t2 - t1) - (t1 - t0)) / steps
+    per_step = max(per_step, 1e-9)
+    scale = full_m / m                           # the oracle's step cost is linear in m
+    return {"value": round(1.0 / (per_step * scale), 6), "unit": "greedy steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"oracle rbd_fit (FP64 numpy) on the same generator at a {grid_sample}x{grid_sample} grid "
+                       f"({m} x {n}, FP32-rounded), {steps} greedy steps timed (difference of a {1 + steps}-step "
+                       f"and a 1-step fit: {per_step:.3f} s/step), scaled by m_full/m_sample = {scale:g}")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path. "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    ensure_built()
+    import numpy as np
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    pf = synth.parametric_field(seed=0, grid=args.grid, n=args.n)
+    m, n = pf.m, pf.n
+    log(f"generating the parametric field {m} x {n} (FP32) on {torch.cuda.get_device_name(0)}")
+    X32 = torch.empty((m, n), dtype=torch.float32, device=dev)
+    pf.fill_device(X32)
+    torch.cuda.synchronize()
+
+    runs = {}
+    log(f"FP32 storage: {args.warmup} warm-up + {args.steps} timed fits, d_max {args.d_max}")
+    runs["f32"] = time_fits(rbd, X32, args.d_max, args.steps, args.warmup)
+    if not args.no_bf16:
+        X16 = X32.to(torch.bfloat16)
+        log("BF16 storage")
+        runs["bf16"] = time_fits(rbd, X16, args.d_max, args.steps, args.warmup)
+
+    phases = None
+    if args.phases:
+        phases = {k: phase_breakdown(rbd, X32 if k == "f32" else X16, args.d_max) for k in runs}
+
+    def summary(r, sx):
+        sec = r["seconds"] / r["fits"]
+        gbs = m * n * sx / (r["xscan_ms"] * 1e-3) / 1e9
+        return sec, gbs
+
+    sec32, gbs32 = summary(runs["f32"], 4)
+    steps_s = runs["f32"]["d"] / sec32
+    out = {
+        "metric": "greedy steps/s + X-scan HBM GB/s (% peak); BF16 vs FP32 at equal error",
+        "value": round(steps_s, 3),
+        "unit": "greedy steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec32 * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"parametric_field {m}x{n} (x_j(s) = sum_k exp(-mu_jk |s-c_k|^2), "
+                               f"{args.grid}^2 grid), FP32 storage, tol 0, d_max {args.d_max}",
+                   "m": m, "n": n, "d_max": args.d_max, "tol": 0.0, "storage": "f32",
+                   "greedy_steps_per_fit": runs["f32"]["d"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs32, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(gbs32 / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "xscan (T(d,:) = xi' X)", "kernel_avg_ms": round(runs["f32"]["xscan_ms"], 4),
+                     "launches_timed": runs["f32"]["xscan_launches"]},
+    }
+    if "bf16" in runs:
+        sec16, gbs16 = summary(runs["bf16"], 2)
+        out["bf16_storage"] = {"value": round(runs["bf16"]["d"] / sec16, 3), "unit": "greedy steps/s",
+                               "ms_per_step": round(sec16 * 1e3, 3),
+                               "xscan_GBs": round(gbs16, 1), "xscan_frac": round(gbs16 / PEAK_HBM_GBS, 4),
+                               "kernel_avg_ms": round(runs["bf16"]["xscan_ms"], 4)}
+    if phases:
+        out["phases"] = phases
+    if not args.no_equal_error:
+        out["equal_error"] = equal_error_report(runs, pf, args.sample_cols)
+    for r in runs.values():
+        del r["bufs"], r["res"]
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(m, n=n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

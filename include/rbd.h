@@ -140,6 +140,35 @@ int rbd_project(const double* Y, int64_t ldy, int64_t m, int32_t d,
                 double* Tv, double* err_v,
                 void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Optional phase timing for measurement tools.  Between rbd_profiler_begin and
+ * rbd_profiler_end, every rbd_fit call made by the calling host thread records
+ * HIP events on its stream around the launches of the phases selected by
+ * `phase_mask` (bit i = phase i below) and at the end of every greedy step.
+ * Events come from a pool owned by the library and reused across calls; no
+ * device memory is allocated.  rbd_profiler_end waits for the last recorded
+ * event, then returns, per phase, the summed kernel time in milliseconds and
+ * the number of launches (arrays of length `nphase`, may be NULL), and for the
+ * last recorded fit the elapsed milliseconds from its start to the end of each
+ * step (`step_end_ms`, up to `nstep` entries; *nstep_out = steps recorded).
+ * Recording adds a few microseconds per event to the stream.
+ */
+enum {
+    RBD_PHASE_COLNORM = 0,   /* diag(X'X) pre-computation (section 3.3)          */
+    RBD_PHASE_INIT = 1,      /* E_0, tau, first column                           */
+    RBD_PHASE_CGS1 = 2,      /* first Gram-Schmidt pass + partial h2              */
+    RBD_PHASE_CGS2 = 3,      /* second pass, norm, break test                     */
+    RBD_PHASE_XSCAN = 4,     /* T(d, :) = xi' X: the stream over X                */
+    RBD_PHASE_UPDATE = 5,    /* error downdate and argmax (eq. (3))               */
+    RBD_PHASE_RESID = 6,     /* exact residual norms of queued columns            */
+    RBD_PHASE_RESID_FINISH = 7,
+    RBD_PHASE_EPILOGUE = 8,
+    RBD_NUM_PHASES = 9
+};
+int rbd_profiler_begin(uint32_t phase_mask);
+int rbd_profiler_end(double* phase_ms, int64_t* phase_launches, int32_t nphase,
+                     double* step_end_ms, int64_t nstep, int64_t* nstep_out);
+
 /* Human-readable text for a return or status code (static storage). */
 const char* rbd_status_string(int code);
 

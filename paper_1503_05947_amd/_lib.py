@@ -16,6 +16,7 @@ RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE = 0, -1, -2, -3,
 # stop reasons
 RBD_STOP_TOL, RBD_STOP_DMAX, RBD_STOP_BREAK = 1, 2, 3
 RBD_MAX_D = 1024
+PHASES = ("colnorm", "init", "cgs1", "cgs2", "xscan", "update", "resid", "resid_finish", "epilogue")
 
 # every symbol include/rbd.h declares, with its ctypes signature
 _i64, _i32, _sz, _vp, _dp = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
@@ -26,6 +27,8 @@ SIGNATURES = {
     "rbd_project_workspace_size": (ctypes.c_int, [_i64, _i32, _i64, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_project": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, ctypes.c_int, _i64, _i64, _vp, _vp,
                                    _vp, _sz, _vp]),
+    "rbd_profiler_begin": (ctypes.c_int, [ctypes.c_uint32]),
+    "rbd_profiler_end": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i64, _vp]),
     "rbd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbd_version": (ctypes.c_char_p, []),
 }
@@ -73,3 +76,39 @@ def project_workspace_size(m: int, d: int, k: int, dtype: int) -> int:
     out = ctypes.c_size_t(0)
     check(load().rbd_project_workspace_size(m, d, k, dtype, ctypes.byref(out)), "rbd_project_workspace_size")
     return out.value
+
+
+class Profiler:
+    """Context manager around rbd_profiler_begin/end (HIP events on the fit's stream)."""
+
+    def __init__(self, phases=PHASES, max_steps=RBD_MAX_D):
+        self.mask = 0
+        for p in phases:
+            self.mask |= 1 << PHASES.index(p)
+        self.max_steps = max_steps
+        self.phase_ms = {}
+        self.launches = {}
+        self.step_end_ms = []
+
+    def __enter__(self):
+        check(load().rbd_profiler_begin(self.mask), "rbd_profiler_begin")
+        return self
+
+    def __exit__(self, *exc):
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        steps = (ctypes.c_double * self.max_steps)()
+        nout = ctypes.c_int64(0)
+        rc = load().rbd_profiler_end(ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(cnt, ctypes.c_void_p), n,
+                                     ctypes.cast(steps, ctypes.c_void_p), self.max_steps, ctypes.byref(nout))
+        if exc[0] is None:
+            check(rc, "rbd_profiler_end")
+        self.phase_ms = {p: ms[i] for i, p in enumerate(PHASES)}
+        self.launches = {p: cnt[i] for i, p in enumerate(PHASES)}
+        self.step_end_ms = [steps[i] for i in range(min(nout.value, self.max_steps))]
+        return False
+
+    def avg_ms(self, phase):
+        c = self.launches.get(phase, 0)
+        return self.phase_ms[phase] / c if c else float("nan")

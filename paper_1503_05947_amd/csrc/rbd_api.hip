@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "../../include/rbd.h"
 #include "rbd_kernels.h"
@@ -127,6 +128,58 @@ int kc_for(int d) {
     return kc;
 }
 
+// ---------------------------------------------------------------------------
+// optional HIP-event phase profiler (per host thread)
+// ---------------------------------------------------------------------------
+struct Profiler {
+    bool on = false;
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Mark { int phase; size_t a, b; };
+    std::vector<Mark> marks;
+    size_t fit_start = 0;
+    std::vector<size_t> steps;      // event index at the end of each step of the current fit
+    bool failed = false;
+
+    hipEvent_t* take(hipStream_t s) {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { failed = true; return nullptr; }
+            pool.push_back(e);
+        }
+        hipEvent_t* e = &pool[used];
+        if (hipEventRecord(*e, s) != hipSuccess) failed = true;
+        ++used;
+        return e;
+    }
+};
+thread_local Profiler g_prof;
+thread_local size_t g_prof_open = 0;
+
+inline void prof_fit_begin(hipStream_t s) {
+    if (!g_prof.on) return;
+    g_prof.steps.clear();
+    g_prof.fit_start = g_prof.used;
+    g_prof.take(s);
+}
+inline void prof_begin(int phase, hipStream_t s) {
+    if (!g_prof.on || !(g_prof.mask & (1u << phase))) return;
+    g_prof_open = g_prof.used;
+    g_prof.take(s);
+}
+inline void prof_end(int phase, hipStream_t s) {
+    if (!g_prof.on || !(g_prof.mask & (1u << phase))) return;
+    const size_t b = g_prof.used;
+    g_prof.take(s);
+    g_prof.marks.push_back({phase, g_prof_open, b});
+}
+inline void prof_step(hipStream_t s) {
+    if (!g_prof.on) return;
+    g_prof.steps.push_back(g_prof.used);
+    g_prof.take(s);
+}
+
 #define RBD_LAUNCH_CHECK()                                   \
     do {                                                     \
         if (hipGetLastError() != hipSuccess) return RBD_EDEVICE; \
@@ -173,17 +226,23 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const size_t sc_lds = sizeof(double) * P.sc_rows;
     const dim3 up_grid(P.up_ncb, P.up_SG);
 
+    prof_fit_begin(s);
     init_state_kernel<<<1, 256, 0, s>>>(st, tickets, P.ntickets, P.D, flist);
     RBD_LAUNCH_CHECK();
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
+    prof_begin(RBD_PHASE_COLNORM, s);
     xscan_kernel<Tx, kScanSqr, 4, false><<<sc_grid, P.sc_tpb, 0, s>>>(X, ldx, P.m, P.n, nullptr, st, Y, P.d_max, 0,
                                                                       P.sc_rows, part, vec_ok);
     RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_COLNORM, s);
+    prof_begin(RBD_PHASE_INIT, s);
     update_kernel<kInit><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, 0, l2, P.up_SG, tickets, e2, base2, T, P.n,
                                                  flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
     RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_INIT, s);
 
     for (int d = 0; d < P.D; ++d) {
+        prof_begin(RBD_PHASE_CGS1, s);
         switch (kc_for(d)) {
             case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
             case 2: launch_cgs1<Tx, 2>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
@@ -192,6 +251,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
             default: launch_cgs1<Tx, 16>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
         }
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_CGS1, s);
+        prof_begin(RBD_PHASE_CGS2, s);
         switch (kc_for(d)) {
             case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
             case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
@@ -200,6 +261,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
             default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
         }
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_CGS2, s);
+        prof_begin(RBD_PHASE_XSCAN, s);
         if (nt)
             xscan_kernel<Tx, kScanDot, 4, true><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y, P.d_max,
                                                                               d, P.sc_rows, part, vec_ok);
@@ -207,21 +270,31 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
             xscan_kernel<Tx, kScanDot, 4, false><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y,
                                                                                P.d_max, d, P.sc_rows, part, vec_ok);
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_XSCAN, s);
+        prof_begin(RBD_PHASE_UPDATE, s);
         update_kernel<kStep><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, d, l2, P.up_SG, tickets, e2, base2, T,
                                                      P.n, flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_UPDATE, s);
+        prof_begin(RBD_PHASE_RESID, s);
         resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n);
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_RESID, s);
+        prof_begin(RBD_PHASE_RESID_FINISH, s);
         resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, rpart, P.n, P.rc_S, flist, e2, base2, P.n, tickets, pivots,
                                                       err_hist, d);
         RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_RESID_FINISH, s);
+        prof_step(s);
     }
     const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
     const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
+    prof_begin(RBD_PHASE_EPILOGUE, s);
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
                                        stop_reason);
     RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_EPILOGUE, s);
     return RBD_OK;
 }
 
@@ -350,6 +423,51 @@ int rbd_project(const double* Y, int64_t ldy, int64_t m, int32_t d, const void* 
             return project_typed<f16_t>(P, Y, ldy, m, d, static_cast<const f16_t*>(V), k, ldv, Tv, err_v, ws, s);
     }
     return RBD_EINVAL;
+}
+
+int rbd_profiler_begin(uint32_t phase_mask) {
+    if (g_prof.on) return RBD_EINVAL;
+    g_prof.on = true;
+    g_prof.mask = phase_mask;
+    g_prof.used = 0;
+    g_prof.marks.clear();
+    g_prof.steps.clear();
+    g_prof.failed = false;
+    return RBD_OK;
+}
+
+int rbd_profiler_end(double* phase_ms, int64_t* phase_launches, int32_t nphase, double* step_end_ms, int64_t nstep,
+                     int64_t* nstep_out) {
+    if (!g_prof.on) return RBD_EINVAL;
+    g_prof.on = false;
+    if (g_prof.failed) return RBD_EDEVICE;
+    if (g_prof.used > 0 && hipEventSynchronize(g_prof.pool[g_prof.used - 1]) != hipSuccess) return RBD_EDEVICE;
+    if (phase_ms)
+        for (int i = 0; i < nphase; ++i) phase_ms[i] = 0.0;
+    if (phase_launches)
+        for (int i = 0; i < nphase; ++i) phase_launches[i] = 0;
+    for (const auto& mk : g_prof.marks) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof.pool[mk.a], g_prof.pool[mk.b]) != hipSuccess) return RBD_EDEVICE;
+        if (mk.phase < nphase) {
+            if (phase_ms) phase_ms[mk.phase] += ms;
+            if (phase_launches) phase_launches[mk.phase] += 1;
+        }
+    }
+    const int64_t ns = (int64_t)g_prof.steps.size();
+    if (nstep_out) *nstep_out = ns;
+    if (step_end_ms) {
+        for (int64_t i = 0; i < ns && i < nstep; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g_prof.pool[g_prof.fit_start], g_prof.pool[g_prof.steps[i]]) != hipSuccess)
+                return RBD_EDEVICE;
+            step_end_ms[i] = ms;
+        }
+    }
+    g_prof.used = 0;
+    g_prof.marks.clear();
+    g_prof.steps.clear();
+    return RBD_OK;
 }
 
 const char* rbd_status_string(int code) {
