@@ -49,7 +49,8 @@ struct FitPlan {
     int rc_rows = 0, rc_S = 0, rc_grid = 0, rf_grid = 0;
     int ntickets = 0;
     // workspace offsets (bytes)
-    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_part,
+    int ntiles = 0;
+    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_part,
         o_l2, o_rpart, total;
 };
 
@@ -85,11 +86,12 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->cg_group = 32;
     P->cg_ngroups = (int)cdiv(P->cg_S, P->cg_group);
 
-    // exact residuals: at most 64 row slabs of a multiple of 64 rows
-    int64_t rrow = std::max<int64_t>(64, cdiv(cdiv(m, 64), 64) * 64);
+    // exact residuals: 64-column tiles of the queue, at most 256 row slabs of a multiple of 128 rows
+    P->ntiles = (int)cdiv(n, 64);
+    int64_t rrow = std::max<int64_t>(128, cdiv(cdiv(m, 256), 128) * 128);
     P->rc_rows = (int)std::min<int64_t>(rrow, INT32_MAX / 2);
     P->rc_S = (int)cdiv(m, rrow);
-    P->rc_grid = (int)std::min<int64_t>(2048, cdiv(n, 64) * P->rc_S);
+    P->rc_grid = (int)std::min<int64_t>(2048, (int64_t)P->ntiles * P->rc_S);
     P->rf_grid = (int)cdiv(n, 256);
 
     P->ntickets = (int)std::max<int64_t>(P->up_ncb + 1, P->cg_ngroups + 1) + 8;
@@ -104,6 +106,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_tickets = take(sizeof(unsigned) * P->ntickets);
     P->o_e2 = take(8 * n);
     P->o_base2 = take(8 * n);
+    P->o_flags = take(4 * n);
     P->o_flist = take(4 * n);
     P->o_bres_v = take(8 * P->up_ncb);
     P->o_bres_i = take(8 * P->up_ncb);
@@ -187,17 +190,25 @@ inline void prof_step(hipStream_t s) {
 
 template <typename Tx, int KC>
 void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, const double* T, State* st,
-                 int d, double* v1, double* part, double* l2, unsigned* tickets, double* h2,
-                 hipStream_t s) {
+                 int d, double* v1, double* part, hipStream_t s) {
     cgs1_kernel<Tx, KC, 4><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, v1, part,
-                                                   std::max(P.D, 1), l2, P.cg_group, tickets, h2);
+                                                   std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
-                 double* v2, double* part, double* l2, unsigned* tickets, double* nu2, hipStream_t s) {
-    cgs2_kernel<KC, 4><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part, l2,
-                                               P.cg_group, tickets, nu2);
+                 double* v2, double* part, hipStream_t s) {
+    cgs2_kernel<KC, 4><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part);
+}
+
+// out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
+// groups of `per`, then the group sums), through `l2` (ceil(rows/per) x ldp).
+void launch_sum_rows(const State* st, const double* part, int64_t ldp, int rows, int per, int64_t len, double* l2,
+                     double* out, int64_t ldo_final, hipStream_t s) {
+    const int groups = (int)cdiv(rows, per);
+    const unsigned gx = (unsigned)cdiv(len, 256);
+    reduce_rows_kernel<<<dim3(gx, groups), 256, 0, s>>>(st, part, ldp, rows, per, len, l2, ldp);
+    reduce_rows_kernel<<<dim3(gx, 1), 256, 0, s>>>(st, l2, ldp, groups, groups, len, out, ldo_final);
 }
 
 template <typename Tx>
@@ -208,13 +219,13 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     unsigned* tickets = reinterpret_cast<unsigned*>(ws + P.o_tickets);
     double* e2 = reinterpret_cast<double*>(ws + P.o_e2);
     double* base2 = reinterpret_cast<double*>(ws + P.o_base2);
+    int* flags = reinterpret_cast<int*>(ws + P.o_flags);
     int* flist = reinterpret_cast<int*>(ws + P.o_flist);
     double* bres_v = reinterpret_cast<double*>(ws + P.o_bres_v);
     int64_t* bres_i = reinterpret_cast<int64_t*>(ws + P.o_bres_i);
     double* v1 = reinterpret_cast<double*>(ws + P.o_v1);
     double* v2 = reinterpret_cast<double*>(ws + P.o_v2);
     double* h2 = reinterpret_cast<double*>(ws + P.o_h2);
-    double* nu2 = reinterpret_cast<double*>(ws + P.o_nu2);
     double* part = reinterpret_cast<double*>(ws + P.o_part);
     double* l2 = reinterpret_cast<double*>(ws + P.o_l2);
     double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
@@ -224,10 +235,11 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const bool nt = (double)P.m * (double)ldx * sizeof(Tx) > 512.0 * 1024 * 1024;
     const dim3 sc_grid(P.sc_tiles, P.sc_S);
     const size_t sc_lds = sizeof(double) * P.sc_rows;
-    const dim3 up_grid(P.up_ncb, P.up_SG);
 
     prof_fit_begin(s);
-    init_state_kernel<<<1, 256, 0, s>>>(st, tickets, P.ntickets, P.D, flist);
+    const int64_t nflags = P.n;
+    init_state_kernel<<<(unsigned)std::min<int64_t>(1024, cdiv(std::max<int64_t>(nflags, P.ntickets), 256)), 256, 0,
+                        s>>>(st, tickets, P.ntickets, P.D, flags, nflags);
     RBD_LAUNCH_CHECK();
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
     prof_begin(RBD_PHASE_COLNORM, s);
@@ -236,30 +248,41 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_COLNORM, s);
     prof_begin(RBD_PHASE_INIT, s);
-    update_kernel<kInit><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, 0, l2, P.up_SG, tickets, e2, base2, T, P.n,
-                                                 flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+    const int up_per = (int)cdiv(P.sc_S, P.up_SG);
+    const dim3 red_grid((unsigned)cdiv(P.n, 256), (unsigned)cdiv(P.sc_S, up_per));
+    const int up_groups = (int)cdiv(P.sc_S, up_per);
+    reduce_rows_kernel<<<red_grid, 256, 0, s>>>(nullptr, part, P.n, P.sc_S, up_per, P.n, l2, P.n);
+    RBD_LAUNCH_CHECK();
+    update_kernel<kInit><<<P.up_ncb, 256, 0, s>>>(P.n, st, 0, l2, up_groups, tickets, e2, base2, T, P.n, flags, flist,
+                                                  bres_v, bres_i, pivots, err_hist, start, tol, rel);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_INIT, s);
 
     for (int d = 0; d < P.D; ++d) {
         prof_begin(RBD_PHASE_CGS1, s);
         switch (kc_for(d)) {
-            case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
-            case 2: launch_cgs1<Tx, 2>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
-            case 4: launch_cgs1<Tx, 4>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
-            case 8: launch_cgs1<Tx, 8>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
-            default: launch_cgs1<Tx, 16>(P, X, ldx, Y, T, st, d, v1, part, l2, tickets, h2, s); break;
+            case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, s); break;
+            case 2: launch_cgs1<Tx, 2>(P, X, ldx, Y, T, st, d, v1, part, s); break;
+            case 4: launch_cgs1<Tx, 4>(P, X, ldx, Y, T, st, d, v1, part, s); break;
+            case 8: launch_cgs1<Tx, 8>(P, X, ldx, Y, T, st, d, v1, part, s); break;
+            default: launch_cgs1<Tx, 16>(P, X, ldx, Y, T, st, d, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
+        if (d > 0) {
+            launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, h2, 0, s);
+            RBD_LAUNCH_CHECK();
+        }
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
         switch (kc_for(d)) {
-            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
-            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
-            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
-            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
-            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, l2, tickets, nu2, s); break;
+            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, s); break;
+            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, s); break;
         }
+        RBD_LAUNCH_CHECK();
+        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
@@ -272,8 +295,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_XSCAN, s);
         prof_begin(RBD_PHASE_UPDATE, s);
-        update_kernel<kStep><<<up_grid, 256, 0, s>>>(part, P.sc_S, P.n, st, d, l2, P.up_SG, tickets, e2, base2, T,
-                                                     P.n, flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        reduce_rows_kernel<<<red_grid, 256, 0, s>>>(st, part, P.n, P.sc_S, up_per, P.n, l2, P.n);
+        RBD_LAUNCH_CHECK();
+        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
+                                                      flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
@@ -311,7 +336,7 @@ bool make_proj_plan(int64_t m, int32_t d, int64_t k, ProjPlan* P) {
     P->rows = (int)cdiv(m, P->S);
     P->rows = (int)(cdiv(P->rows, 16) * 16);
     P->S = (int)cdiv(m, P->rows);
-    int64_t rrow = std::max<int64_t>(64, cdiv(cdiv(m, 64), 64) * 64);
+    int64_t rrow = std::max<int64_t>(128, cdiv(cdiv(m, 64), 128) * 128);
     P->rc_rows = (int)rrow;
     P->rc_S = (int)cdiv(m, rrow);
     P->rc_grid = (int)std::min<int64_t>(2048, cdiv(k, 64) * P->rc_S);

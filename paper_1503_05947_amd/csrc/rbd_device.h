@@ -95,10 +95,45 @@ template <> struct Ld<f16_t> {
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+// One step of a DPP reduction: v += v[lane given by CTRL] on the rows in ROW_MASK
+// (other rows add 0).  Doubles move as two 32-bit halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+// Sums of R independent values over the 64 lanes of a wave, interleaved step
+// by step; the result is uniform (read from lane 63).  Fixed order: quads,
+// half rows, rows of 16, then rows 0+1 and 2+3, then the two halves.
+// Every lane of the wave must be active.
+template <int R>
+__device__ __forceinline__ void wave_sum_n(double (&v)[R]) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0xB1, 0xf>(v[u]);   // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x4E, 0xf>(v[u]);   // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x141, 0xf>(v[u]);  // row_half_mirror
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x140, 0xf>(v[u]);  // row_mirror
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x142, 0xa>(v[u]);  // row_bcast:15
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x143, 0xc>(v[u]);  // row_bcast:31
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v[u]), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v[u]), 63);
+        v[u] = __hiloint2double(hi, lo);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    double a[1] = {v};
+    wave_sum_n<1>(a);
+    return a[0];
 }
 
 // (value, index) maximum; ties go to the lower index.  NaN never wins.
@@ -157,35 +192,6 @@ __device__ __forceinline__ bool last_to_arrive(unsigned* counter, unsigned expec
     }
     __syncthreads();
     return last;
-}
-
-// Two-level deterministic reduction of per-block rows.
-//   part  : nblk rows of `len` doubles (row stride ldp); block `blk` wrote row blk
-//   l2    : ceil(nblk / group) rows (stride ldp) of scratch
-//   out   : len doubles, written by the single block for which this returns true
-// Order: out[k] = sum_g ( sum_{b in group g, ascending} part[b][k] ), g ascending.
-// Uses tickets[0 .. ngroups] (ngroups + 1 counters).
-__device__ __forceinline__ bool grid_reduce_rows(const double* part, int64_t ldp, int nblk, int len,
-                                                 double* l2, int group, unsigned* tickets, double* out,
-                                                 int blk) {
-    const int ngroups = (nblk + group - 1) / group;
-    const int g = blk / group;
-    const int gsz = min(group, nblk - g * group);
-    if (!last_to_arrive(&tickets[g], (unsigned)gsz)) return false;
-    for (int k = threadIdx.x; k < len; k += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < gsz; ++b) s += part[(int64_t)(g * group + b) * ldp + k];
-        l2[(int64_t)g * ldp + k] = s;
-    }
-    if (!last_to_arrive(&tickets[ngroups], (unsigned)ngroups)) return false;
-    for (int k = threadIdx.x; k < len; k += blockDim.x) {
-        double s = 0.0;
-        for (int q = 0; q < ngroups; ++q) s += l2[(int64_t)q * ldp + k];
-        out[k] = s;
-    }
-    __threadfence();
-    __syncthreads();
-    return true;
 }
 
 }  // namespace rbd

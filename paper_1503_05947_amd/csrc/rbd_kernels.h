@@ -1,17 +1,27 @@
 // Kernels of the greedy loop of Reduced Basis Decomposition (Algorithm 1,
-// section 3.1) with A = I (eq. (3)).  One greedy step is six stream-ordered
-// kernels; every kernel reads the device-side stop flag first, so steps past
-// the end of the loop cost one empty launch each and the host never waits.
+// section 3.1) with A = I (eq. (3)).  One greedy step is a fixed sequence of
+// stream-ordered kernels; every kernel reads the device-side stop flag first,
+// so steps past the end of the loop cost one empty launch each and the host
+// never waits.
 //
-//   cgs1   v1 = x_p - Y h1 with h1 = T(0:d, p)   (first Gram-Schmidt pass;
-//          h1 = Y' x_p is already a column of T), fused with the partial
-//          sums of h2 = Y' v1
-//   cgs2   v2 = v1 - Y h2 (second pass), nu = ||v2||, step 2.2's break test
-//   xscan  xi = v2 / nu written to Y(:, d); T(d, :) partials = xi' X per row slab
-//   update T(d, :) = sum of partials; e_j^2 -= T(d, j)^2; queue columns whose
-//          downdated error fell below kappa * (last exact value); argmax
-//   resid  exact ||x_j - Y T(:, j)||^2 for queued columns (a small FP64 GEMM)
-//   resid_finish  store exact values, argmax, stop test of step 2.4
+//   cgs1    v1 = x_p - Y h1 with h1 = T(0:d, p)   (first Gram-Schmidt pass;
+//           h1 = Y' x_p is already a column of T), fused with per-block
+//           partial sums of h2 = Y' v1
+//   reduce  h2 = fixed-order sum of the partials (two small launches)
+//   cgs2    v2 = v1 - Y h2 (second pass) and per-block partial ||v2||^2
+//   nu      nu = ||v2||, step 2.2's break test
+//   xscan   xi = v2 / nu written to Y(:, d); partial xi' X per row slab
+//   reduce  combine slab partials into slab-group partials
+//   update  T(d, :); e_j^2 -= T(d, j)^2; queue columns whose downdated error
+//           fell below kappa * (last exact value); lowest-index argmax
+//   resid   exact ||x_j - Y T(:, j)||^2 for the queued columns (FP64 GEMM)
+//   resid_finish  store the exact values, argmax, stop test of step 2.4
+//
+// Wide kernels (thousands of workgroups) never synchronise across the grid:
+// a device-scope release fence per workgroup writes back the XCD's L2 and
+// costs far more than a kernel boundary.  Grid-wide combination therefore
+// happens in separate launches, and ticket counters (last workgroup to arrive
+// finishes the job) are used only by kernels with a few dozen workgroups.
 #pragma once
 
 #include "rbd_device.h"
@@ -36,9 +46,12 @@ __device__ __forceinline__ void finish_step(State* st, int d, double vmax, int64
 }
 
 // ---------------------------------------------------------------------------
-__global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, int D, int* flist) {
-    for (int i = threadIdx.x; i < ntickets; i += blockDim.x) tickets[i] = 0u;
-    if (threadIdx.x == 0) {
+__global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, int D, int* flags, int64_t nflags) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < ntickets; i += stride) tickets[i] = 0u;
+    for (int64_t i = gid; i < nflags; i += stride) flags[i] = 0;
+    if (gid == 0) {
         st->d = 0; st->p = 0; st->stop = 0; st->status = RBD_OK; st->nflag = 0; st->D = D;
         st->nonfinite = 0; st->pad0 = 0;
         st->tau = 0.0; st->E0 = 0.0; st->nu = 0.0; st->inv_nu = 0.0;
@@ -126,33 +139,28 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
 }
 
 // ---------------------------------------------------------------------------
-// update: combine the scan partials of each column (two levels, fixed order),
-// then either initialise the errors (INIT) or downdate them (STEP), and take
-// the lowest-index argmax.  Grid (column blocks of 256, slab groups SG).
+// update: finish the column sums (slab groups, fixed order), then either
+// initialise the errors (INIT) or downdate them (STEP), and take the
+// lowest-index argmax.  One block per 256 columns; the last block to arrive
+// combines the block maxima and closes the step.
 // ---------------------------------------------------------------------------
 enum { kInit = 0, kStep = 1 };
 
 template <int MODE>
-__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ part, int S, int64_t n,
-                                                      State* __restrict__ st, int d, double* __restrict__ l2,
-                                                      int SG, unsigned* __restrict__ tickets,
+__global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restrict__ st, int d,
+                                                      const double* __restrict__ l2, int SG,
+                                                      unsigned* __restrict__ tickets,
                                                       double* __restrict__ e2, double* __restrict__ base2,
-                                                      double* __restrict__ T, int64_t ldt, int* __restrict__ flist,
+                                                      double* __restrict__ T, int64_t ldt, int* __restrict__ flags,
+                                                      int* __restrict__ flist,
                                                       double* __restrict__ bres_v, int64_t* __restrict__ bres_i,
                                                       int64_t* __restrict__ pivots, double* __restrict__ err_hist,
                                                       int64_t start, double tol, int rel) {
     if (MODE == kStep && st->stop) return;
     __shared__ double sv[4];
     __shared__ int64_t si[4];
-    const int cb = blockIdx.x, g = blockIdx.y, ncb = gridDim.x;
+    const int cb = blockIdx.x, ncb = gridDim.x;
     const int64_t j = (int64_t)cb * blockDim.x + threadIdx.x;
-    const int s0 = (int)((int64_t)g * S / SG), s1 = (int)((int64_t)(g + 1) * S / SG);
-    if (j < n) {
-        double s = 0.0;
-        for (int q = s0; q < s1; ++q) s += part[(int64_t)q * n + j];
-        l2[(int64_t)g * n + j] = s;
-    }
-    if (!last_to_arrive(&tickets[cb], (unsigned)SG)) return;
 
     double best = -1.0;
     int64_t bi = INT64_MAX;
@@ -177,8 +185,8 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
             }
             e2[j] = e;
             if (e < kRefresh * b) {
-                const int pos = atomicAdd(&st->nflag, 1);
-                flist[pos] = (int)j;
+                flags[j] = 1;
+                atomicAdd(&st->nflag, 1);
             }
         }
         if (e == e) { best = e; bi = j; }
@@ -186,6 +194,30 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
     block_argmax(best, bi, sv, si);
     if (threadIdx.x == 0) { bres_v[cb] = best; bres_i[cb] = bi; }
     if (!last_to_arrive(&tickets[ncb], (unsigned)ncb)) return;
+    if (MODE == kStep && __hip_atomic_load(&st->nflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+        // list the queued columns in ascending order (so neighbouring columns
+        // share the cache lines of X) and clear their flags
+        __shared__ int scan[256];
+        const int64_t per = (n + blockDim.x - 1) / blockDim.x;
+        const int64_t a = (int64_t)threadIdx.x * per, b = min(n, a + per);
+        int cnt = 0;
+        for (int64_t c = a; c < b; ++c) cnt += flags[c];
+        scan[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int add = (int)threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += add;
+            __syncthreads();
+        }
+        int pos = scan[threadIdx.x] - cnt;
+        for (int64_t c = a; c < b; ++c)
+            if (flags[c]) {
+                flist[pos++] = (int)c;
+                flags[c] = 0;
+            }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         double v = -1.0;
         int64_t i = INT64_MAX;
@@ -220,8 +252,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int
                                                     const double* __restrict__ T, int64_t ldt,
                                                     State* __restrict__ st, int d, int rows_per_blk,
                                                     double* __restrict__ v1, double* __restrict__ part,
-                                                    int64_t ldp, double* __restrict__ l2, int group,
-                                                    unsigned* __restrict__ tickets, double* __restrict__ h2) {
+                                                    int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -255,17 +286,16 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int
             }
         }
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
+        for (int u = 0; u < RU; ++u)
 #pragma unroll
             for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
-            dot[u] = wave_sum(dot[u]);
-            const int64_t r = rb + u;
-            const double v = xv[u] - dot[u];
-            if (r < r1) {
-                if (lane == 0) v1[r] = v;
+        wave_sum_n<RU>(dot);
 #pragma unroll
-                for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
-            }
+        for (int u = 0; u < RU; ++u) {
+            const double v = xv[u] - dot[u];   // rows past the end have y = 0
+#pragma unroll
+            for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
+            if (lane == u && rb + u < r1) v1[rb + u] = v;
         }
     }
     if (d == 0) return;
@@ -277,7 +307,6 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int
         __syncthreads();
     }
     for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
-    grid_reduce_rows(part, ldp, gridDim.x, d, l2, group, tickets, h2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,9 +316,7 @@ template <int KC, int RU>
 __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
                                                     State* __restrict__ st, int d, int rows_per_blk,
                                                     const double* __restrict__ v1, const double* __restrict__ h2,
-                                                    double* __restrict__ v2, double* __restrict__ part,
-                                                    double* __restrict__ l2, int group,
-                                                    unsigned* __restrict__ tickets, double* __restrict__ nu2) {
+                                                    double* __restrict__ v2, double* __restrict__ part) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -314,37 +341,72 @@ __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y,
                 y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
             }
         }
+        double dot[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            double dot = 0.0;
+            dot[u] = 0.0;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) dot = fma(y[u][c], hs[lane + kWave * c], dot);
-            dot = wave_sum(dot);
-            const int64_t r = rb + u;
-            const double v = vv[u] - dot;
-            if (r < r1 && lane == 0) {
-                v2[r] = v;
+            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
+        }
+        wave_sum_n<RU>(dot);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const double v = vv[u] - dot[u];
+            if (lane == u && rb + u < r1) {
+                v2[rb + u] = v;
                 nacc = fma(v, v, nacc);
             }
         }
     }
-    const double s = block_sum(lane == 0 ? nacc : 0.0, sred);
+    const double s = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (grid_reduce_rows(part, 1, gridDim.x, 1, l2, group, tickets, nu2, blockIdx.x)) {
-        if (threadIdx.x == 0) {
-            const double nu = sqrt(nu2[0]);
-            st->nu = nu;
-            if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
-            else st->inv_nu = 1.0 / nu;
-        }
+}
+
+// ---------------------------------------------------------------------------
+// nu: nu = ||v2|| from the cgs2 partials (one block, fixed order) and step
+// 2.2's test: ||v|| < eps_R (or ||v|| = 0) keeps the d vectors found so far.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S) {
+    if (st->stop) return;
+    __shared__ double sred[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < S; i += blockDim.x) s += part[i];
+    s = block_sum(s, sred);
+    if (threadIdx.x == 0) {
+        const double nu = sqrt(s);
+        st->nu = nu;
+        if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
+        else st->inv_nu = 1.0 / nu;
     }
 }
 
 // ---------------------------------------------------------------------------
-// resid: partial squared residual norms of selected columns,
+// reduce_rows: out[g * ldo + c] = sum over rows r of group g (rows g*per ..
+// g*per+per-1, ascending) of part[r * ldp + c], for c < len.  Grid
+// (ceil(len / blockDim), groups).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_rows_kernel(const State* __restrict__ st,
+                                                           const double* __restrict__ part, int64_t ldp,
+                                                           int rows, int per, int64_t len,
+                                                           double* __restrict__ out, int64_t ldo) {
+    if (st && st->stop) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= len) return;
+    const int r0 = blockIdx.y * per, r1 = min(rows, r0 + per);
+    double s = 0.0;
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += part[(int64_t)r * ldp + c];
+    out[(int64_t)blockIdx.y * ldo + c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// resid: partial squared residual norms of listed columns,
 //   part[s * ldp + jj] = sum_{i in slab s} (X[i, c] - sum_{k<K} Y[i, k] C[k, c])^2,
-// c = J ? J[jj] : jj, for jj < count.  64 x 64 output tiles, FP64 FMA.
-// Work items (column group, slab) are strided over a fixed grid.
+// c = J ? J[jj] : jj, for jj < count (count = *count_dev when given, else
+// count_host).  An FP64 GEMM with 128 x 128 output tiles (8 x 8 per thread,
+// operands staged in LDS 16 deep in k), the subtraction from X and the column
+// sums of squares fused.  Work items (column tile, slab) are strided over a
+// fixed grid; each writes its own partial, so the result is deterministic.
 // ---------------------------------------------------------------------------
 template <typename Tx>
 __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
@@ -355,64 +417,66 @@ __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, in
                                                      double* __restrict__ part, int64_t ldp) {
     const int cnt = count_dev ? *count_dev : count_host;
     if (cnt == 0) return;
-    __shared__ double Ys[64][17];
-    __shared__ double Cs[16][65];
-    __shared__ double red[16][65];
-    __shared__ int cols[64];
+    constexpr int TM = 128, TN = 64, KB = 16;
+    __shared__ double Ys[TM][KB + 1];
+    __shared__ double Cs[KB][TN + 1];
+    __shared__ int cols[TN];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int njg = (cnt + 63) / 64;
-    const int nwork = njg * nslab;
+    const int ntiles = (cnt + TN - 1) / TN;
+    const int nwork = ntiles * nslab;
     for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
-        const int jg = wk % njg, s = wk / njg;
+        const int t = wk % ntiles, s = wk / ntiles;
         __syncthreads();
-        if (tid < 64) {
-            const int jj = jg * 64 + tid;
+        if (tid < TN) {
+            const int jj = t * TN + tid;
             cols[tid] = (jj < cnt) ? (J ? J[jj] : jj) : -1;
         }
         __syncthreads();
         const int64_t rbeg = (int64_t)s * rows_per_slab;
         const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
-        double rs[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t row0 = rbeg; row0 < rend; row0 += 64) {
-            double acc[4][4];
+        double rs[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) rs[b] = 0.0;
+        for (int64_t row0 = rbeg; row0 < rend; row0 += TM) {
+            double acc[8][4];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int k0 = 0; k0 < K; k0 += 16) {
+            for (int k0 = 0; k0 < K; k0 += KB) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < (TM * KB) / 256; ++q) {
                     const int e = tid + 256 * q;
-                    const int rr = e >> 4, kk = e & 15;
+                    const int rr = e / KB, kk = e % KB;
                     const int64_t row = row0 + rr;
                     const int k = k0 + kk;
                     Ys[rr][kk] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
                 }
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < (TN * KB) / 256; ++q) {
                     const int e = tid + 256 * q;
-                    const int kk = e >> 6, cc = e & 63;
+                    const int kk = e / TN, cc = e % TN;
                     const int k = k0 + kk;
                     const int col = cols[cc];
                     Cs[kk][cc] = (k < K && col >= 0) ? C[(int64_t)k * ldc + col] : 0.0;
                 }
                 __syncthreads();
 #pragma unroll
-                for (int kk = 0; kk < 16; ++kk) {
-                    double yv[4], cv[4];
+                for (int kk = 0; kk < KB; ++kk) {
+                    double yv[8], cv[4];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) yv[a] = Ys[ty + 16 * a][kk];
+                    for (int a = 0; a < 8; ++a) yv[a] = Ys[ty + 16 * a][kk];
 #pragma unroll
                     for (int b = 0; b < 4; ++b) cv[b] = Cs[kk][tx + 16 * b];
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < 8; ++a)
 #pragma unroll
                         for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], cv[b], acc[a][b]);
                 }
                 __syncthreads();
             }
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < 8; ++a) {
                 const int64_t row = row0 + ty + 16 * a;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
@@ -424,13 +488,16 @@ __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, in
                 }
             }
         }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) red[ty][tx + 16 * b] = rs[b];
+        // column sums over the 16 row groups, in order
         __syncthreads();
-        if (tid < 64) {
+        double* red = &Ys[0][0];   // reuse: 16 x 64 doubles fit in Ys (128 x 17)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) red[ty * TN + tx + 16 * b] = rs[b];
+        __syncthreads();
+        if (tid < TN) {
             double sum = 0.0;
-            for (int t = 0; t < 16; ++t) sum += red[t][tid];
-            const int jj = jg * 64 + tid;
+            for (int q = 0; q < 16; ++q) sum += red[q * TN + tid];
+            const int jj = t * TN + tid;
             if (jj < cnt) part[(int64_t)s * ldp + jj] = sum;
         }
     }
@@ -452,6 +519,7 @@ __global__ __launch_bounds__(256) void resid_finish_kernel(State* __restrict__ s
     const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jj < cnt) {
         double s = 0.0;
+#pragma unroll 8
         for (int q = 0; q < nslab; ++q) s += part[(int64_t)q * ldp + jj];
         const int j = J[jj];
         e2[j] = s;
@@ -460,7 +528,7 @@ __global__ __launch_bounds__(256) void resid_finish_kernel(State* __restrict__ s
     if (!last_to_arrive(&tickets[0], gridDim.x)) return;
     double v = -1.0;
     int64_t i = INT64_MAX;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) argmax_merge(v, i, e2[j], j);
+    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) argmax_merge(v, i, e2[c], c);
     block_argmax(v, i, sv, si);
     if (threadIdx.x == 0) {
         finish_step(st, d, v, i, pivots, err_hist);
