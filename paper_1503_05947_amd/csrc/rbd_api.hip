@@ -40,7 +40,7 @@ struct FitPlan {
     int D = 0, d_max = 0;
     rbd_dtype xt = RBD_F32;
     // X-scan
-    int sc_tpb = 256, sc_tiles = 1, sc_rows = 0, sc_S = 0;
+    int sc_tpb = 256, sc_ch = 1, sc_tiles = 1, sc_rows = 0, sc_S = 0;
     // update (combine partials, downdate, argmax)
     int up_ncb = 0, up_SG = 1;
     // Gram-Schmidt passes
@@ -65,12 +65,19 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->D = (int)std::min<int64_t>(d_max, std::min(m, n));
     if (P->D > RBD_MAX_D) return false;
 
-    // X-scan: 16-byte loads, 64..256 threads per column tile, ~2048 workgroups
+    // X-scan: 16-byte loads.  Long-lived workgroups stream best (measured on
+    // MI355X at 1048576 x 4096: 512-1024 workgroups of 2048-row slabs reach
+    // 99% of a plain read stream).  4- and 8-byte types give each thread up to
+    // 4 column chunks so a workgroup covers whole rows; 2-byte types keep one
+    // chunk and 8 rows in flight instead.
     const int N = vec_elems(xt);
     const int64_t nvec = cdiv(n, N);
     P->sc_tpb = nvec >= 256 ? 256 : (nvec >= 128 ? 128 : 64);
-    P->sc_tiles = (int)cdiv(nvec, P->sc_tpb);
-    int64_t rows = cdiv(m * P->sc_tiles, 2048);
+    const bool narrow = elem_bytes(xt) == 2;
+    P->sc_ch = narrow ? 1 : (nvec >= 4 * 256 ? 4 : (nvec >= 2 * 256 ? 2 : 1));
+    P->sc_tiles = (int)cdiv(nvec, (int64_t)P->sc_tpb * P->sc_ch);
+    const int64_t target_wg = narrow ? 1024 : 512;
+    int64_t rows = cdiv(m * P->sc_tiles, target_wg);
     rows = std::max<int64_t>(16, std::min<int64_t>(rows, 4096));
     P->sc_rows = (int)rows;
     P->sc_S = (int)cdiv(m, rows);
@@ -188,6 +195,32 @@ inline void prof_step(hipStream_t s) {
         if (hipGetLastError() != hipSuccess) return RBD_EDEVICE; \
     } while (0)
 
+// X-scan launch for one plan: CH column chunks per thread (4/8-byte types),
+// or one chunk with 8 rows in flight (2-byte types).
+template <typename Tx, int MODE>
+void launch_xscan(const FitPlan& P, const Tx* X, int64_t ldx, const double* v2, State* st, double* Y, int dcol,
+                  double* part, int vec_ok, bool nt, hipStream_t s) {
+    const dim3 grid(P.sc_tiles, P.sc_S);
+    const size_t lds = MODE == kScanDot ? sizeof(double) * P.sc_rows : 0;
+#define RBD_XSCAN(U, NT, CH)                                                                                 \
+    xscan_kernel<Tx, MODE, U, NT, CH><<<grid, P.sc_tpb, lds, s>>>(X, ldx, P.m, P.n, v2, st, Y, P.d_max, dcol, \
+                                                                  P.sc_rows, part, vec_ok)
+    if (sizeof(Tx) == 2) {
+        if (nt) RBD_XSCAN(8, true, 1);
+        else RBD_XSCAN(8, false, 1);
+    } else if (P.sc_ch == 4) {
+        if (nt) RBD_XSCAN(4, true, 4);
+        else RBD_XSCAN(4, false, 4);
+    } else if (P.sc_ch == 2) {
+        if (nt) RBD_XSCAN(4, true, 2);
+        else RBD_XSCAN(4, false, 2);
+    } else {
+        if (nt) RBD_XSCAN(4, true, 1);
+        else RBD_XSCAN(4, false, 1);
+    }
+#undef RBD_XSCAN
+}
+
 template <typename Tx, int KC>
 void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, const double* T, State* st,
                  int d, double* v1, double* part, hipStream_t s) {
@@ -233,8 +266,6 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const int N = Ld<Tx>::N;
     const int vec_ok = (ldx % N == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     const bool nt = (double)P.m * (double)ldx * sizeof(Tx) > 512.0 * 1024 * 1024;
-    const dim3 sc_grid(P.sc_tiles, P.sc_S);
-    const size_t sc_lds = sizeof(double) * P.sc_rows;
 
     prof_fit_begin(s);
     const int64_t nflags = P.n;
@@ -243,8 +274,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     RBD_LAUNCH_CHECK();
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
     prof_begin(RBD_PHASE_COLNORM, s);
-    xscan_kernel<Tx, kScanSqr, 4, false><<<sc_grid, P.sc_tpb, 0, s>>>(X, ldx, P.m, P.n, nullptr, st, Y, P.d_max, 0,
-                                                                      P.sc_rows, part, vec_ok);
+    launch_xscan<Tx, kScanSqr>(P, X, ldx, nullptr, st, Y, 0, part, vec_ok, nt, s);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_COLNORM, s);
     prof_begin(RBD_PHASE_INIT, s);
@@ -286,12 +316,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
-        if (nt)
-            xscan_kernel<Tx, kScanDot, 4, true><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y, P.d_max,
-                                                                              d, P.sc_rows, part, vec_ok);
-        else
-            xscan_kernel<Tx, kScanDot, 4, false><<<sc_grid, P.sc_tpb, sc_lds, s>>>(X, ldx, P.m, P.n, v2, st, Y,
-                                                                               P.d_max, d, P.sc_rows, part, vec_ok);
+        launch_xscan<Tx, kScanDot>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_XSCAN, s);
         prof_begin(RBD_PHASE_UPDATE, s);

@@ -59,11 +59,13 @@ __global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, in
 }
 
 // ---------------------------------------------------------------------------
-// X-scan: per row slab, acc_j = sum_i w_i x_ij (DOT, w = xi) or sum_i x_ij^2 (SQR).
-// Grid (column tiles, row slabs); each thread owns Ld<Tx>::N adjacent columns
-// and streams the slab's rows with 16-byte loads, U rows in flight.
+// X-scan: per row slab, acc_j = sum_i w_i x_ij (DOT, w = xi) or sum_i x_ij^2
+// (SQR).  Grid (column tiles, row slabs).  Each thread owns CH chunks of
+// Ld<Tx>::N adjacent columns, blockDim * N columns apart, and streams the
+// slab's rows with 16-byte loads, U rows in flight.  The slab's xi values are
+// staged in LDS (every lane reads the same address: a broadcast).
 // ---------------------------------------------------------------------------
-template <typename Tx, int MODE, int U, bool NT>
+template <typename Tx, int MODE, int U, bool NT, int CH>
 __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
                                                      int64_t n, const double* __restrict__ v2,
                                                      State* __restrict__ st, double* __restrict__ Y,
@@ -71,6 +73,7 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
                                                      double* __restrict__ part, int vec_ok) {
     if (MODE == kScanDot && st->stop) return;
     using L = Ld<Tx>;
+    using R = typename L::raw;
     constexpr int N = L::N;
     extern __shared__ double xi_s[];
     const int tile = blockIdx.x, slab = blockIdx.y;
@@ -86,56 +89,74 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
         }
         __syncthreads();
     }
-    const int64_t c0 = ((int64_t)tile * blockDim.x + threadIdx.x) * N;
-    if (c0 >= n) return;
-    double acc[N];
+    const int64_t cstep = (int64_t)blockDim.x * N;
+    const int64_t cbase = (int64_t)tile * cstep * CH + (int64_t)threadIdx.x * N;
+    // chunk q covers columns cbase + q*cstep .. +N-1: full (vector), partial (scalar) or empty
+    bool full[CH];
+    int ncols[CH];
 #pragma unroll
-    for (int q = 0; q < N; ++q) acc[q] = 0.0;
-    const Tx* p = X + r0 * ldx + c0;
-    if (vec_ok && c0 + N <= n) {
-        using R = typename L::raw;
-        int r = 0;
-        for (; r + U <= nr; r += U) {
-            R raw[U];
+    for (int q = 0; q < CH; ++q) {
+        const int64_t c = cbase + q * cstep;
+        ncols[q] = (int)max((int64_t)0, min((int64_t)N, n - c));
+        full[q] = vec_ok && ncols[q] == N;
+    }
+    double acc[CH][N];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const R* a = reinterpret_cast<const R*>(p + (int64_t)(r + u) * ldx);
-                raw[u] = NT ? __builtin_nontemporal_load(a) : *a;
-            }
+    for (int q = 0; q < CH; ++q)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+        for (int e = 0; e < N; ++e) acc[q][e] = 0.0;
+    const Tx* p = X + r0 * ldx + cbase;
+    int r = 0;
+    for (; r + U <= nr; r += U) {
+        R raw[U][CH];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < CH; ++q)
+                if (full[q]) {
+                    const R* a = reinterpret_cast<const R*>(p + (int64_t)(r + u) * ldx + q * cstep);
+                    raw[u][q] = NT ? __builtin_nontemporal_load(a) : *a;
+                }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double w = (MODE == kScanDot) ? xi_s[r + u] : 0.0;
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
                 double x[N];
-                L::cvt(raw[u], x);
-                if (MODE == kScanDot) {
-                    const double w = xi_s[r + u];
-#pragma unroll
-                    for (int q = 0; q < N; ++q) acc[q] = fma(w, x[q], acc[q]);
+                if (full[q]) {
+                    L::cvt(raw[u][q], x);
                 } else {
 #pragma unroll
-                    for (int q = 0; q < N; ++q) acc[q] = fma(x[q], x[q], acc[q]);
+                    for (int e = 0; e < N; ++e)
+                        x[e] = e < ncols[q] ? L::one(p + (int64_t)(r + u) * ldx + q * cstep + e) : 0.0;
                 }
-            }
-        }
-        for (; r < nr; ++r) {
-            double x[N];
-            L::cvt(*reinterpret_cast<const R*>(p + (int64_t)r * ldx), x);
-            const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
 #pragma unroll
-            for (int q = 0; q < N; ++q) acc[q] = (MODE == kScanDot) ? fma(w, x[q], acc[q]) : fma(x[q], x[q], acc[q]);
-        }
-    } else {
-        const int nc = (int)min((int64_t)N, n - c0);
-        for (int r = 0; r < nr; ++r) {
-            const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
-            for (int q = 0; q < nc; ++q) {
-                const double x = L::one(p + (int64_t)r * ldx + q);
-                acc[q] = (MODE == kScanDot) ? fma(w, x, acc[q]) : fma(x, x, acc[q]);
+                for (int e = 0; e < N; ++e)
+                    acc[q][e] = (MODE == kScanDot) ? fma(w, x[e], acc[q][e]) : fma(x[e], x[e], acc[q][e]);
             }
         }
     }
-    double* out = part + (int64_t)slab * n + c0;
-    const int nc = (int)min((int64_t)N, n - c0);
-    for (int q = 0; q < nc; ++q) out[q] = acc[q];
+    for (; r < nr; ++r) {
+        const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            double x[N];
+            if (full[q]) {
+                L::cvt(*reinterpret_cast<const R*>(p + (int64_t)r * ldx + q * cstep), x);
+            } else {
+#pragma unroll
+                for (int e = 0; e < N; ++e) x[e] = e < ncols[q] ? L::one(p + (int64_t)r * ldx + q * cstep + e) : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < N; ++e)
+                acc[q][e] = (MODE == kScanDot) ? fma(w, x[e], acc[q][e]) : fma(x[e], x[e], acc[q][e]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        double* out = part + (int64_t)slab * n + cbase + q * cstep;
+        for (int e = 0; e < ncols[q]; ++e) out[e] = acc[q][e];
+    }
 }
 
 // ---------------------------------------------------------------------------
