@@ -221,17 +221,22 @@ void launch_xscan(const FitPlan& P, const Tx* X, int64_t ldx, const double* v2, 
 #undef RBD_XSCAN
 }
 
+// Rows of Y in flight per wave: short rows (small d) are latency-bound, so keep
+// more of them in flight; long rows are limited by registers.
+constexpr int rows_in_flight(int KC) { return KC <= 2 ? 8 : (KC <= 8 ? 4 : 2); }
+
 template <typename Tx, int KC>
 void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, const double* T, State* st,
                  int d, double* v1, double* part, hipStream_t s) {
-    cgs1_kernel<Tx, KC, 4><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, v1, part,
-                                                   std::max(P.D, 1));
+    cgs1_kernel<Tx, KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                    P.cg_rows, v1, part, std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
                  double* v2, double* part, hipStream_t s) {
-    cgs2_kernel<KC, 4><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part);
+    cgs2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2,
+                                                                part);
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in

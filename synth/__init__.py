@@ -216,6 +216,17 @@ class ParametricField:
             out = out + A[k][a] * B[k][b]
         return out
 
+    def columns(self, cols) -> np.ndarray:
+        """FP64 values of the given columns (all rows), same operation order as ``rows``."""
+        cols = np.asarray(cols, dtype=np.int64)
+        A, B = self.factors(cols=cols)
+        idx = np.arange(self.m)
+        a, b = idx // self.grid, idx % self.grid
+        out = A[0][a] * B[0][b]
+        for k in range(1, A.shape[0]):
+            out = out + A[k][a] * B[k][b]
+        return out
+
     def full(self) -> np.ndarray:
         A, B = self.factors()
         return self.rows(np.arange(self.m), A, B)

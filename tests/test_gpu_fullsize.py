@@ -1,0 +1,61 @@
+"""Parity at full size, in the launch configuration bench.py times: the parametric
+field 1,048,576 x 4096, tol 0, d_max 512, FP32 and BF16 storage.
+
+The oracle cannot run at this size, so the checks use outputs the host can form
+one at a time (T and the residual norms of sampled columns, whose stored values
+the host regenerates bit for bit) and properties that hold at any size
+(orthonormality of sampled basis pairs, T(:, pivots) upper triangular with
+diagonal E_{k-1}, distinct pivots, non-increasing history).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_parametric_field_full_size(dtype):
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    print(f"[gpu] parametric field 1048576 x 4096 dtype={dtype} d_max=512", flush=True)
+    pf = synth.parametric_field(seed=0)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    X = torch.empty((pf.m, pf.n), dtype=tdt, device="cuda:0")
+    pf.fill_device(X)
+    res = rbd.fit(X, tol=0.0, d_max=512)
+    del X
+    torch.cuda.empty_cache()
+    assert res.d == 512 and res.stop == "dmax"
+    piv = res.pivots.cpu().numpy()
+    hist = res.err_hist.cpu().numpy()
+    col_err = res.col_err.cpu().numpy()
+    T = res.T.cpu().numpy()
+    E0 = hist[0]
+    assert len(set(piv.tolist())) == 512
+    assert np.all(np.diff(hist) <= 1e-9 * E0)
+    # T(:, pivots) is upper triangular with diagonal E_{k-1}
+    B = T[:, piv]
+    assert np.max(np.abs(np.diag(B) - hist[:512])) <= 1e-9 * E0
+    assert np.max(np.abs(np.tril(B, -1))) <= 1e-9 * E0
+    # sampled columns, regenerated on the host exactly as stored
+    g = np.random.default_rng(7)
+    J = np.unique(np.concatenate([g.choice(pf.n, 5, replace=False), piv[[0, 1, 511]]]))
+    Xj = synth.quantize(pf.columns(J), dtype)[1]
+    Y = res.Y.cpu().numpy()
+    Tj = Y.T @ Xj
+    nx = np.linalg.norm(Xj, axis=0)
+    assert np.max(np.abs(Tj - T[:, J]) / nx) <= 1e-12
+    R = Xj - Y @ T[:, J]
+    true_err = np.linalg.norm(R, axis=0)
+    true_err[np.isin(J, piv)] = 0.0
+    assert np.max(np.abs(true_err - col_err[J])) <= 1e-5 * E0
+    # the certified indicator is accurate relative to itself as well
+    live = true_err > 0
+    assert np.max(np.abs(true_err[live] - col_err[J][live]) / true_err[live]) <= 1e-4
+    # sampled orthonormality, including the last basis vectors
+    cols = [0, 1, 2, 255, 256, 509, 510, 511]
+    G = Y[:, cols].T @ Y[:, cols]
+    assert np.max(np.abs(G - np.eye(len(cols)))) <= 1e-12
