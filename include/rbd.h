@@ -141,6 +141,72 @@ int rbd_project(const double* Y, int64_t ldy, int64_t m, int32_t d,
                 void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Batched fits: many independent matrices of different sizes in one
+ * persistent launch (Algorithm 1 applied to each, with the same readings and
+ * certified errors as rbd_fit).  Limits: m_b <= 4096 rows, d_max <= 256.
+ *
+ * Packed layouts (all row-major, offsets in elements, assigned in batch order
+ * by rbd_batch_plan): X holds X_b (m_b x n_b, ld n_b) back to back; Y holds
+ * Y_b (m_b x d_max); T holds T_b (d_max x n_b); col_err holds n_b values per
+ * matrix; pivots is batch x d_max; err_hist is batch x (d_max + 1); d_out and
+ * status hold one int32 per matrix.  Unused basis columns / rows of T are
+ * zeroed, pivots past d are -1, as for rbd_fit.
+ */
+typedef struct {
+    int64_t x_elems, y_elems, t_elems, c_elems; /* sizes of the packed X, Y, T, col_err buffers */
+    int64_t max_m, max_n;                       /* largest m_b and n_b                           */
+    size_t workspace_bytes;                     /* device workspace rbd_fit_batched needs          */
+} rbd_batch_sizes;
+
+/* Workgroup shape of the persistent launch: threads per workgroup (64, 128,
+ * 256, 512 or 1024; one workgroup handles one matrix at a time) and
+ * workgroups per compute unit (1..16). */
+typedef struct {
+    int32_t threads;
+    int32_t wg_per_cu;
+} rbd_batch_config;
+
+/*
+ * rbd_batch_plan -- host-only.  From the sizes m[b], n[b] (host arrays of
+ * `batch` entries) fills `desc` (host, batch x 8 int64: per-matrix sizes and
+ * offsets) and `order` (host, batch int32: processing order, largest
+ * m_b * n_b * min(d_max, m_b, n_b) first), and the buffer sizes.  The caller
+ * copies desc and order to the device.  Returns RBD_OK or RBD_EINVAL.
+ */
+int rbd_batch_plan(const int64_t* m, const int64_t* n, int32_t batch, int32_t d_max, int64_t* desc,
+                   int32_t* order, rbd_batch_sizes* sizes);
+
+/*
+ * rbd_fit_batched -- fits every matrix of the batch in one persistent launch
+ * on `stream`.  desc / order: device copies of rbd_batch_plan's arrays;
+ * max_m: sizes.max_m.  tol, mode, d_max as for rbd_fit (one setting for all
+ * matrices).  Returns RBD_OK, RBD_EINVAL, RBD_EWORKSPACE or RBD_EDEVICE;
+ * per-matrix non-finite input is reported in status[b].
+ */
+int rbd_fit_batched(const void* X, rbd_dtype xt, const int64_t* desc, const int32_t* order, int32_t batch,
+                    double tol, rbd_tol_mode mode, int32_t d_max, rbd_batch_config cfg,
+                    double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                    int32_t* d_out, int32_t* status, int64_t max_m,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rbd_batched_autotune -- empirical choice of rbd_batch_config: runs every
+ * candidate (threads 128..1024 x 1, 2, 4 workgroups per compute unit) twice on
+ * the sub-batch order[0], order[s], order[2s], ... (s = sample_stride), keeps
+ * the fastest second run, and writes it to *best (and the 12 times in ms to
+ * trial_ms when not NULL, threads-major; -1 for a shape that cannot be
+ * launched, e.g. for lack of LDS).  Overwrites the sampled matrices'
+ * outputs and WAITS for the stream.  Same arguments otherwise as
+ * rbd_fit_batched.
+ */
+int rbd_batched_autotune(const void* X, rbd_dtype xt, const int64_t* desc, const int32_t* order, int32_t batch,
+                         double tol, rbd_tol_mode mode, int32_t d_max, int32_t sample_stride,
+                         double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                         int32_t* d_out, int32_t* status, int64_t max_m,
+                         void* workspace, size_t workspace_bytes, void* stream,
+                         rbd_batch_config* best, double* trial_ms);
+
+/*
  * Optional phase timing for measurement tools.  Between rbd_profiler_begin and
  * rbd_profiler_end, every rbd_fit call made by the calling host thread records
  * HIP events on its stream around the launches of the phases selected by

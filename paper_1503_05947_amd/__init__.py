@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import (LibraryMissing, RBD_MAX_D, RBD_STOP_BREAK, RBD_STOP_DMAX, RBD_STOP_TOL, load,
                    status_string)
 
-__all__ = ["fit", "fit_into", "FitBuffers", "FitResult", "project", "load", "status_string",
+__all__ = ["fit", "fit_into", "FitBuffers", "FitResult", "project", "fit_batched", "BatchPlan", "BatchConfig",
+           "load", "status_string",
            "LibraryMissing", "RBD_MAX_D"]
 
 STOP_NAMES = {0: "error", RBD_STOP_TOL: "tol", RBD_STOP_DMAX: "dmax", RBD_STOP_BREAK: "break"}
@@ -143,3 +144,128 @@ def project(Y, V, stream=None):
         _lib.check(rc, "rbd_project")
         s.synchronize()
     return Tv, err
+
+
+# ---------------------------------------------------------------------------
+# batched fits
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchConfig:
+    threads: int
+    wg_per_cu: int
+
+
+class BatchPlan:
+    """Sizes, packed device buffers and workspace of one batch of matrices.
+
+    ``ms``/``ns`` give every matrix's shape; X_b is stored row-major with
+    leading dimension n_b, back to back in batch order (``pack`` does this).
+    """
+
+    def __init__(self, ms, ns, d_max: int, dtype, device):
+        import ctypes
+
+        import numpy as np
+        torch = _torch()
+        self.ms = np.asarray(ms, dtype=np.int64)
+        self.ns = np.asarray(ns, dtype=np.int64)
+        self.batch = len(self.ms)
+        self.d_max, self.dtype = int(d_max), dtype
+        self.device = torch.device(device)
+        desc = np.zeros((self.batch, 8), dtype=np.int64)
+        order = np.zeros(self.batch, dtype=np.int32)
+        sizes = _lib.BatchSizes()
+        rc = load().rbd_batch_plan(self.ms.ctypes.data, self.ns.ctypes.data, self.batch, self.d_max,
+                                   desc.ctypes.data, order.ctypes.data, ctypes.byref(sizes))
+        _lib.check(rc, "rbd_batch_plan")
+        self.desc_host, self.order_host, self.sizes = desc, order, sizes
+        dev = self.device
+        self.desc = torch.from_numpy(desc).to(dev)
+        self.order = torch.from_numpy(order).to(dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.Y = torch.empty(sizes.y_elems, **f64)
+        self.T = torch.empty(sizes.t_elems, **f64)
+        self.col_err = torch.empty(sizes.c_elems, **f64)
+        self.pivots = torch.empty((self.batch, self.d_max), dtype=torch.int64, device=dev)
+        self.err_hist = torch.empty((self.batch, self.d_max + 1), **f64)
+        self.ints = torch.empty((2, self.batch), dtype=torch.int32, device=dev)   # d, status
+        self.workspace = torch.empty(max(int(sizes.workspace_bytes), 256), dtype=torch.uint8, device=dev)
+        self.config = None
+
+    def pack(self, mats):
+        """Concatenate row-major matrices (device tensors of the plan's dtype) in batch order."""
+        torch = _torch()
+        for b, A in enumerate(mats):
+            if tuple(A.shape) != (int(self.ms[b]), int(self.ns[b])) or A.dtype != self.dtype:
+                raise ValueError(f"matrix {b} does not match the plan")
+        return torch.cat([A.contiguous().reshape(-1) for A in mats]).to(self.device)
+
+    def _args(self, Xp, tol, rel):
+        if Xp.dim() != 1 or Xp.numel() != self.sizes.x_elems or Xp.dtype != self.dtype:
+            raise ValueError("packed X does not match the plan")
+        ints = self.ints.data_ptr()
+        return (Xp.data_ptr(), dtype_code(self.dtype), self.desc.data_ptr(), self.order.data_ptr(), self.batch,
+                float(tol), _lib.RBD_TOL_REL if rel else _lib.RBD_TOL_ABS, self.d_max)
+
+    def _outs(self):
+        ints = self.ints.data_ptr()
+        return (self.Y.data_ptr(), self.T.data_ptr(), self.pivots.data_ptr(), self.col_err.data_ptr(),
+                self.err_hist.data_ptr(), ints, ints + 4 * self.batch, int(self.sizes.max_m),
+                self.workspace.data_ptr(), self.workspace.numel())
+
+    def autotune(self, Xp, tol=0.0, rel=False, sample_stride=16, stream=None):
+        """Pick the workgroup shape by timing every candidate on a sub-batch (waits for the device)."""
+        import ctypes
+        torch = _torch()
+        best = _lib.BatchConfig()
+        times = (ctypes.c_double * 12)()
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            rc = load().rbd_batched_autotune(*self._args(Xp, tol, rel), int(sample_stride), *self._outs(),
+                                             s.cuda_stream, ctypes.byref(best), ctypes.cast(times, ctypes.c_void_p))
+        _lib.check(rc, "rbd_batched_autotune")
+        self.config = BatchConfig(best.threads, best.wg_per_cu)
+        self.trials = {(t, w): times[i * 3 + k] for i, t in enumerate((128, 256, 512, 1024))
+                       for k, w in enumerate((1, 2, 4))}
+        return self.config
+
+    def run(self, Xp, tol=0.0, rel=False, config=None, stream=None):
+        """Enqueue the batched fit (no wait)."""
+        torch = _torch()
+        cfg = config or self.config or BatchConfig(256, 2)
+        c = _lib.BatchConfig(int(cfg.threads), int(cfg.wg_per_cu))
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            a = self._args(Xp, tol, rel)
+            rc = load().rbd_fit_batched(*a, c, *self._outs(), s.cuda_stream)
+        _lib.check(rc, "rbd_fit_batched")
+
+    def results(self):
+        """Per-matrix FitResult views (waits for the device)."""
+        torch = _torch()
+        torch.cuda.current_stream(self.device).synchronize()
+        ds, sts = (v.tolist() for v in self.ints.cpu())
+        out = []
+        for b in range(self.batch):
+            if sts[b] != _lib.RBD_OK:
+                out.append(None)
+                continue
+            dsc = self.desc_host[b]
+            m, n, d = int(dsc[0]), int(dsc[1]), int(ds[b])
+            Y = self.Y[dsc[3]: dsc[3] + m * self.d_max].view(m, self.d_max)[:, :d]
+            T = self.T[dsc[4]: dsc[4] + self.d_max * n].view(self.d_max, n)[:d]
+            out.append(FitResult(Y=Y, T=T, pivots=self.pivots[b, :d], col_err=self.col_err[dsc[5]: dsc[5] + n],
+                                 err_hist=self.err_hist[b, : d + 1], d=d, stop=""))
+        return out
+
+
+def fit_batched(mats, tol: float = 0.0, d_max: int = 64, rel: bool = False, config=None, autotune: bool = False):
+    """Fit every matrix in ``mats`` (device tensors, one dtype) in one persistent launch.
+
+    Returns (list of FitResult or None for matrices with non-finite data, BatchPlan)."""
+    plan = BatchPlan([A.shape[0] for A in mats], [A.shape[1] for A in mats], d_max, mats[0].dtype, mats[0].device)
+    Xp = plan.pack(mats)
+    if autotune and config is None:
+        plan.autotune(Xp, tol=tol, rel=rel)
+    plan.run(Xp, tol=tol, rel=rel, config=config)
+    return plan.results(), plan

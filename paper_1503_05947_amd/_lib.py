@@ -27,11 +27,31 @@ SIGNATURES = {
     "rbd_project_workspace_size": (ctypes.c_int, [_i64, _i32, _i64, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_project": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, ctypes.c_int, _i64, _i64, _vp, _vp,
                                    _vp, _sz, _vp]),
+    "rbd_batch_plan": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "rbd_fit_batched": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i32, _dp, ctypes.c_int, _i32, None,
+                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "rbd_batched_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i32, _dp, ctypes.c_int, _i32, _i32,
+                                            _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "rbd_profiler_begin": (ctypes.c_int, [ctypes.c_uint32]),
     "rbd_profiler_end": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i64, _vp]),
     "rbd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbd_version": (ctypes.c_char_p, []),
 }
+
+
+
+class BatchSizes(ctypes.Structure):
+    _fields_ = [("x_elems", ctypes.c_int64), ("y_elems", ctypes.c_int64), ("t_elems", ctypes.c_int64),
+                ("c_elems", ctypes.c_int64), ("max_m", ctypes.c_int64), ("max_n", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
+
+
+# the by-value struct argument of rbd_fit_batched
+SIGNATURES["rbd_fit_batched"][1][8] = BatchConfig
 
 _lib = None
 

@@ -15,6 +15,8 @@
 namespace rbd {
 
 constexpr int kWave = 64;
+constexpr int kStopError = 4;           // internal stop code: non-finite input
+constexpr double kRefresh = 0x1p-20;    // kappa: re-evaluate a column exactly when e^2 < kappa * (last exact e^2)
 
 // ---------------------------------------------------------------------------
 // loop state kept in device memory (one per rbd_fit call)

@@ -28,8 +28,6 @@
 
 namespace rbd {
 
-constexpr int kStopError = 4;           // internal: non-finite input
-constexpr double kRefresh = 0x1p-20;    // kappa: re-evaluate when e^2 < kappa * base^2
 
 enum { kScanDot = 0, kScanSqr = 1 };
 

@@ -311,8 +311,12 @@ def batched_sizes(seed: int = 0, count: int = 4096, lo: int = 64, hi: int = 1024
 
 
 def batched_matrix(seed: int, index: int, m: int, n: int, decade: float = 8.0) -> np.ndarray:
-    """X_b = U diag(10^(-i/decade)) V^T with orthonormal U, V of rank min(m, n)."""
-    r = min(m, n)
+    """X_b = U diag(10^(-i/decade)) V^T with orthonormal U, V of rank min(m, n, 17 decade).
+
+    Singular values beyond i = 17 decade are below 1e-17 of the largest, under
+    the resolution of FP64 (and far under FP32) storage, so they are omitted.
+    """
+    r = min(m, n, int(17 * decade))
     U = haar(rng(4, seed * 1_000_003 + index, S_U), m, r)
     V = haar(rng(4, seed * 1_000_003 + index, S_V), n, r)
     sig = 10.0 ** (-np.arange(r) / decade)

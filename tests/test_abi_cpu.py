@@ -124,3 +124,32 @@ def test_missing_library_fails_loudly(tmp_path):
             _lib.load(str(tmp_path / "nope.so"))
         finally:
             _lib._lib = _lib._lib_saved
+
+
+def test_batch_plan_offsets_and_order(lib):
+    import numpy as np
+    from paper_1503_05947_amd import _lib
+    ms = np.array([5, 300, 40, 7], dtype=np.int64)
+    ns = np.array([9, 20, 40, 1], dtype=np.int64)
+    desc = np.zeros((4, 8), dtype=np.int64)
+    order = np.zeros(4, dtype=np.int32)
+    sizes = _lib.BatchSizes()
+    import ctypes
+    rc = lib.rbd_batch_plan(ms.ctypes.data, ns.ctypes.data, 4, 16, desc.ctypes.data, order.ctypes.data,
+                            ctypes.byref(sizes))
+    assert rc == _lib.RBD_OK
+    D = np.minimum(16, np.minimum(ms, ns))
+    assert desc[:, 0].tolist() == ms.tolist() and desc[:, 1].tolist() == ns.tolist()
+    assert desc[:, 7].tolist() == D.tolist()
+    assert desc[:, 2].tolist() == [0, 45, 45 + 6000, 45 + 6000 + 1600]              # X offsets
+    assert desc[:, 3].tolist() == [0, 5 * 16, 305 * 16, 345 * 16]                  # Y offsets
+    assert desc[:, 4].tolist() == [0, 16 * 9, 16 * 29, 16 * 69]                    # T offsets
+    assert sizes.x_elems == 45 + 6000 + 1600 + 7 and sizes.max_m == 300 and sizes.max_n == 40
+    cost = ms * ns * D
+    assert order.tolist() == sorted(range(4), key=lambda b: -cost[b])
+    assert sizes.workspace_bytes >= 256 + 8 * int((D * ms + 2 * ns).sum())
+    bad = np.array([5000, 3], dtype=np.int64)
+    assert lib.rbd_batch_plan(bad.ctypes.data, bad.ctypes.data, 2, 16, desc.ctypes.data, order.ctypes.data,
+                              ctypes.byref(sizes)) == _lib.RBD_EINVAL
+    assert lib.rbd_batch_plan(ms.ctypes.data, ns.ctypes.data, 4, 300, desc.ctypes.data, order.ctypes.data,
+                              ctypes.byref(sizes)) == _lib.RBD_EINVAL
