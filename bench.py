@@ -51,6 +51,9 @@ def parse():
                     help="also time the batched fit: 4096 matrices, m, n log-uniform in [64, 1024], "
                          "spectrum 10^(-i/8), FP32, relative tol 1e-6")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--backward", action="store_true",
+                    help="also time the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
+                         "fixed from a tol-0 fit, G ~ N(0,1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one elementwise kernel over 1 GiB (read 1 GiB, write 1 GiB) before the fits, "
                          "as the reference for hardware traffic counters")
@@ -274,6 +277,54 @@ def batched_section(rbd, count, K, W, d_max=128, tol=1e-6):
                     "but the matrices in flight at any time fit in it, so effective bandwidth can exceed HBM's"}
 
 
+def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True):
+    import numpy as np
+    import torch
+
+    import synth
+    log(f"backward: bump field {m} x {n}, d = {d}")
+    w = synth.bump_field(0, m=m, n=n, d_max=d)
+    Xs, Xv = synth.quantize(w.X, "f32")
+    del w
+    dev = torch.device("cuda:0")
+    X = torch.from_numpy(Xs).to(dev)
+    G64 = synth.cotangent(0, m, n)
+    G = torch.from_numpy(G64).to(dev)
+    res = rbd.fit(X, tol=0.0, d_max=d)
+    fwd = []
+    for _ in range(W):
+        rbd.reconstruct_backward(X, G, res.Y, res.T, res.pivots)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        rbd.reconstruct_backward(X, G, res.Y, res.T, res.pivots)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / K
+    t0 = time.perf_counter()
+    for _ in range(K):
+        Z = rbd.reconstruct(res.Y, res.T)
+    torch.cuda.synchronize()
+    fsec = (time.perf_counter() - t0) / K
+    flops = 8.0 * m * n * d + 6.0 * m * d * d
+    out = {"m": m, "n": n, "d": d, "storage": "f32", "cotangent": "f64",
+           "ms": round(sec * 1e3, 3), "algorithmic_GFLOP": round(flops / 1e9, 2),
+           "TFLOPs": round(flops / sec / 1e12, 2), "peak_TFLOPs_f64_matrix": 78.6,
+           "frac": round(flops / sec / 78.6e12, 4),
+           "reconstruct_ms": round(fsec * 1e3, 3), "reconstruct_TFLOPs": round(2.0 * m * n * d / fsec / 1e12, 2)}
+    if cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        oracle.reconstruction_grad(Xv, res.pivots.cpu().numpy(), G64)
+        out["cpu_baseline"] = {"value_ms": round((time.perf_counter() - t0) * 1e3, 1), "cores": int(cores),
+                               "kind": "oracle", "sample": "the full-size gradient, once"}
+    return out
+
+
 def batched_cpu_baseline(count=4096, sample=24, d_max=128, tol=1e-6):
     import numpy as np
     import oracle
@@ -416,6 +467,9 @@ def main():
         out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup)
         if not args.no_cpu_baseline:
             out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
+    if args.backward:
+        torch.cuda.empty_cache()
+        out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(m, n=n)

@@ -207,6 +207,37 @@ int rbd_batched_autotune(const void* X, rbd_dtype xt, const int64_t* desc, const
                          rbd_batch_config* best, double* trial_ms);
 
 /*
+ * rbd_reconstruct -- uncompress (section 3.1): Z = Y T, i.e. X(:, j) ~
+ * Y T(:, j) for every column.  Y: m x d (ld ldy >= d), T: d x n (ld ldt >= n),
+ * Z: m x n (ld ldz >= n), all FP64 device memory.  An FP64 GEMM on the matrix
+ * cores; needs no workspace.  Returns RBD_OK, RBD_EINVAL or RBD_EDEVICE.
+ */
+int rbd_reconstruct(const double* Y, int64_t ldy, int64_t m, int32_t d, const double* T, int64_t ldt, int64_t n,
+                    double* Z, int64_t ldz, void* stream);
+
+/*
+ * rbd_reconstruct_backward -- gradient of L = <G, Z>, Z = Y Y' X (the
+ * reconstruction of X by its own fit), with respect to X, holding the pivots
+ * fixed.  With A = X(:, pivots) = Y R (R = T(:, pivots), upper triangular):
+ *   dX = Y (Y'G) + scatter_pivots( (Ybar + Y copyltu(-Ybar'Y)) R^{-T} ),
+ *   Ybar = G T' + X (G'Y),   copyltu(M) = tril(M) + tril(M, -1)'.
+ *
+ *   X       m x n, ld ldx, storage xt (the matrix that was fitted)
+ *   G       m x n, ld ldg, FP64 or FP32 (the cotangent of Z)
+ *   Y, T    the fit's basis (m x d, ld ldy) and coefficients (d x n, ld ldt)
+ *   pivots  d int64 (device), the fit's pivots (distinct)
+ *   dX      m x n FP64 output, ld lddx (overwritten)
+ *   workspace  rbd_reconstruct_backward_workspace_size() bytes, 256-aligned
+ * 1 <= d <= min(m, n, RBD_MAX_D).  Returns RBD_OK, RBD_EINVAL, RBD_EWORKSPACE
+ * or RBD_EDEVICE.
+ */
+int rbd_reconstruct_backward_workspace_size(int64_t m, int64_t n, int32_t d, size_t* bytes);
+int rbd_reconstruct_backward(const void* X, rbd_dtype xt, int64_t ldx, const void* G, rbd_dtype gt, int64_t ldg,
+                             const double* Y, int64_t ldy, const double* T, int64_t ldt, const int64_t* pivots,
+                             int64_t m, int64_t n, int32_t d, double* dX, int64_t lddx,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Optional phase timing for measurement tools.  Between rbd_profiler_begin and
  * rbd_profiler_end, every rbd_fit call made by the calling host thread records
  * HIP events on its stream around the launches of the phases selected by

@@ -195,3 +195,44 @@ def rbd_project(Y, V):
 def reconstruct(Y, T):
     """Uncompress: X(:, j) ~ Y T(:, j) (section 3.1)."""
     return np.asarray(Y, dtype=np.float64) @ np.asarray(T, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# differentiating the reconstruction with the pivots held fixed
+# ---------------------------------------------------------------------------
+
+def basis_from_pivots(X, pivots):
+    """Y, R with X(:, pivots) = Y R, Y orthonormal, R upper triangular with a
+    positive diagonal: the basis Algorithm 1 builds from these columns."""
+    A = np.asarray(X, dtype=np.float64)[:, np.asarray(pivots)]
+    Q, R = np.linalg.qr(A)
+    s = np.sign(np.diag(R))
+    s[s == 0] = 1.0
+    return Q * s[None, :], R * s[:, None]
+
+
+def reconstruction_loss(X, pivots, G):
+    """L = <G, Y Y' X> with Y the basis spanned by the pivot columns of X."""
+    X = np.asarray(X, dtype=np.float64)
+    Y, _R = basis_from_pivots(X, pivots)
+    return float(np.sum(np.asarray(G, dtype=np.float64) * (Y @ (Y.T @ X))))
+
+
+def reconstruction_grad(X, pivots, G):
+    """dL/dX for L = <G, Y Y' X>, pivots fixed: the direct term Y Y'G plus the
+    adjoint of the QR factorisation X(:, P) = Y R with Rbar = 0,
+    Abar = (Ybar + Y copyltu(-Ybar'Y)) R^{-T}, Ybar = G T' + X G'Y."""
+    import scipy.linalg as sla
+    X = np.asarray(X, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    P = np.asarray(pivots)
+    Y, R = basis_from_pivots(X, P)
+    T = Y.T @ X
+    YtG = Y.T @ G
+    grad = Y @ YtG
+    Ybar = G @ T.T + X @ YtG.T
+    M = -(Ybar.T @ Y)
+    S = np.tril(M) + np.tril(M, -1).T
+    Abar = sla.solve_triangular(R, (Ybar + Y @ S).T, lower=False).T      # Abar R^T = W
+    grad[:, P] += Abar
+    return grad

@@ -20,6 +20,7 @@ from ._lib import (LibraryMissing, RBD_MAX_D, RBD_STOP_BREAK, RBD_STOP_DMAX, RBD
                    status_string)
 
 __all__ = ["fit", "fit_into", "FitBuffers", "FitResult", "project", "fit_batched", "BatchPlan", "BatchConfig",
+           "reconstruct", "reconstruct_backward", "rbd_reconstruction",
            "load", "status_string",
            "LibraryMissing", "RBD_MAX_D"]
 
@@ -269,3 +270,85 @@ def fit_batched(mats, tol: float = 0.0, d_max: int = 64, rel: bool = False, conf
         plan.autotune(Xp, tol=tol, rel=rel)
     plan.run(Xp, tol=tol, rel=rel, config=config)
     return plan.results(), plan
+
+
+# ---------------------------------------------------------------------------
+# reconstruction and its backward (pivots fixed)
+# ---------------------------------------------------------------------------
+def reconstruct(Y, T, stream=None):
+    """Uncompress: Z = Y T (FP64), section 3.1."""
+    torch = _torch()
+    _check_matrix(Y, "Y")
+    _check_matrix(T, "T")
+    m, d = Y.shape
+    n = T.shape[1]
+    if T.shape[0] != d or Y.dtype != torch.float64 or T.dtype != torch.float64:
+        raise ValueError("Y (m x d) and T (d x n) must be float64")
+    Z = torch.empty((m, n), dtype=torch.float64, device=Y.device)
+    with torch.cuda.device(Y.device):
+        s = stream if stream is not None else torch.cuda.current_stream(Y.device)
+        rc = load().rbd_reconstruct(Y.data_ptr(), Y.stride(0), m, d, T.data_ptr(), T.stride(0), n, Z.data_ptr(),
+                                    Z.stride(0), s.cuda_stream)
+    _lib.check(rc, "rbd_reconstruct")
+    return Z
+
+
+def reconstruct_backward(X, G, Y, T, pivots, stream=None):
+    """dL/dX (FP64) for L = <G, Y Y' X> with the pivots held fixed."""
+    import ctypes
+    torch = _torch()
+    for A, nm in ((X, "X"), (G, "G"), (Y, "Y"), (T, "T")):
+        _check_matrix(A, nm)
+    m, n = X.shape
+    d = Y.shape[1]
+    if G.shape != X.shape or Y.shape[0] != m or T.shape != (d, n) or pivots.numel() != d:
+        raise ValueError("shape mismatch")
+    if G.dtype not in (torch.float64, torch.float32):
+        raise TypeError("G must be float64 or float32")
+    piv = pivots.to(torch.int64).contiguous()
+    ws = ctypes.c_size_t(0)
+    _lib.check(load().rbd_reconstruct_backward_workspace_size(m, n, d, ctypes.byref(ws)),
+               "rbd_reconstruct_backward_workspace_size")
+    dX = torch.empty((m, n), dtype=torch.float64, device=X.device)
+    work = torch.empty(max(ws.value, 256), dtype=torch.uint8, device=X.device)
+    with torch.cuda.device(X.device):
+        s = stream if stream is not None else torch.cuda.current_stream(X.device)
+        rc = load().rbd_reconstruct_backward(X.data_ptr(), dtype_code(X.dtype), X.stride(0), G.data_ptr(),
+                                             dtype_code(G.dtype), G.stride(0), Y.data_ptr(), Y.stride(0),
+                                             T.data_ptr(), T.stride(0), piv.data_ptr(), m, n, d, dX.data_ptr(),
+                                             dX.stride(0), work.data_ptr(), work.numel(), s.cuda_stream)
+    _lib.check(rc, "rbd_reconstruct_backward")
+    return dX
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class RBDReconstruct(torch.autograd.Function):
+        """Z = Y Y' X where (Y, T) = RBD(X): the forward runs the greedy fit and the
+        reconstruction; the backward differentiates with the pivots held fixed."""
+
+        @staticmethod
+        def forward(ctx, X, tol, d_max, rel):
+            res = fit(X.detach(), tol=tol, d_max=d_max, rel=rel)
+            ctx.save_for_backward(X.detach(), res.Y, res.T, res.pivots)
+            return reconstruct(res.Y, res.T)
+
+        @staticmethod
+        def backward(ctx, G):
+            X, Y, T, piv = ctx.saved_tensors
+            dX = reconstruct_backward(X, G.contiguous(), Y, T, piv)
+            return dX.to(X.dtype), None, None, None
+
+    return RBDReconstruct
+
+
+_RBDReconstruct = None
+
+
+def rbd_reconstruction(X, tol: float = 0.0, d_max: int = 64, rel: bool = False):
+    """Differentiable Z = Y Y' X (torch.autograd); gradients hold the pivots fixed."""
+    global _RBDReconstruct
+    if _RBDReconstruct is None:
+        _RBDReconstruct = _autograd_function()
+    return _RBDReconstruct.apply(X, tol, d_max, rel)

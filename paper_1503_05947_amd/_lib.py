@@ -32,6 +32,10 @@ SIGNATURES = {
                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp]),
     "rbd_batched_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i32, _dp, ctypes.c_int, _i32, _i32,
                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
+    "rbd_reconstruct": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, _i64, _i64, _vp, _i64, _vp]),
+    "rbd_reconstruct_backward_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
+    "rbd_reconstruct_backward": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _vp, ctypes.c_int, _i64, _vp, _i64, _vp,
+                                                _i64, _vp, _i64, _i64, _i32, _vp, _i64, _vp, _sz, _vp]),
     "rbd_profiler_begin": (ctypes.c_int, [ctypes.c_uint32]),
     "rbd_profiler_end": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i64, _vp]),
     "rbd_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -1,0 +1,116 @@
+// FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64) for the dense
+// contractions of the reconstruction Y T and its backward:
+//   C = alpha * op(A) op(B) + beta * C      (op = identity or transpose)
+// A and B are row-major with leading dimensions lda / ldb and may be stored
+// in FP64, FP32, BF16 or FP16 (widened exactly to FP64 when staged).
+//
+// Tiling: 128 x 128 output tile per workgroup (4 waves, 64 x 64 each, i.e.
+// 4 x 4 MFMA tiles of 16 x 16), k staged through LDS 16 deep.  MFMA operand
+// layout (16x16x4, wave64): lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16); accumulator register r of lane l holds C(4 r + l / 16,
+// l % 16).  With `splits` > 1 the k range is divided over blockIdx.z and each
+// split writes its own partial tile to `part` (split-major, M x N each), to be
+// summed in a fixed order by gemm_split_sum_kernel.
+#pragma once
+
+#include "rbd_device.h"
+
+namespace rbd {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGM = 128, kGN = 128, kGK = 16;
+
+template <bool TA, bool TB, typename TAe, typename TBe>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                        const TAe* __restrict__ A, int64_t lda,
+                                                        const TBe* __restrict__ B, int64_t ldb, double beta,
+                                                        double* __restrict__ C, int64_t ldc, int64_t kchunk,
+                                                        double* __restrict__ part) {
+    __shared__ double As[kGK][kGM + 1];
+    __shared__ double Bs[kGK][kGN + 1];
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;       // this wave's 64 x 64 sub-tile
+    const int64_t row0 = (int64_t)blockIdx.y * kGM, col0 = (int64_t)blockIdx.x * kGN;
+    const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
+        // stage op(A)(row0 .. +128, k0 .. +16) and op(B)(k0 .. +16, col0 .. +128)
+#pragma unroll
+        for (int q = 0; q < (kGM * kGK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            int i, k;
+            if (TA) { k = e / kGM; i = e % kGM; }     // A stored K x M: rows of A are k
+            else { i = e / kGK; k = e % kGK; }        // A stored M x K
+            const int64_t gi = row0 + i, gk = k0 + k;
+            double v = 0.0;
+            if (gi < M && gk < ke) v = TA ? Ld<TAe>::one(A + gk * lda + gi) : Ld<TAe>::one(A + gi * lda + gk);
+            As[k][i] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < (kGN * kGK) / 256; ++q) {
+            const int e = tid + 256 * q;
+            int j, k;
+            if (TB) { j = e / kGK; k = e % kGK; }     // B stored N x K
+            else { k = e / kGN; j = e % kGN; }        // B stored K x N
+            const int64_t gj = col0 + j, gk = k0 + k;
+            double v = 0.0;
+            if (gj < N && gk < ke) v = TB ? Ld<TBe>::one(B + gj * ldb + gk) : Ld<TBe>::one(B + gk * ldb + gj);
+            Bs[k][j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kGK; ks += 4) {
+            double af[4], bf[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) af[a] = As[ks + lane / 16][wr + a * 16 + lane % 16];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + lane / 16][wc + b * 16 + lane % 16];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double* out = part ? part + (int64_t)blockIdx.z * M * N : nullptr;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = row0 + wr + a * 16 + 4 * r + lane / 16;
+                const int64_t gj = col0 + wc + b * 16 + lane % 16;
+                if (gi < M && gj < N) {
+                    if (out) {
+                        out[gi * N + gj] = acc[a][b][r];
+                    } else {
+                        const double prev = beta != 0.0 ? C[gi * ldc + gj] : 0.0;
+                        C[gi * ldc + gj] = alpha * acc[a][b][r] + beta * prev;
+                    }
+                }
+            }
+}
+
+// C = alpha * sum_{s < splits} part[s] + beta * C (fixed order over s).
+__global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, int64_t N, int splits, double alpha,
+                                                              const double* __restrict__ part, double beta,
+                                                              double* __restrict__ C, int64_t ldc) {
+    const int64_t tot = M * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < splits; ++q) s += part[(int64_t)q * tot + e];
+        const int64_t i = e / N, j = e % N;
+        const double prev = beta != 0.0 ? C[i * ldc + j] : 0.0;
+        C[i * ldc + j] = alpha * s + beta * prev;
+    }
+}
+
+}  // namespace rbd
