@@ -115,6 +115,23 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
             void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * rbd_fit_weighted -- Algorithm 1 with the A-norm of section 3.2 for a general
+ * diagonal A = diag(weights) ("part of each data entry needs to be preserved
+ * better"): the basis Y and T = Y'X are built exactly as by rbd_fit, but
+ * every error of step 2.3 (hence E_0, the relative tolerance, the pivot
+ * choice, col_err and err_hist) is ||x_j - Y T(:, j)||_A, eq. (3).
+ *   weights  m FP64 device values, all > 0 (not checked on the device); the
+ *            other arguments, outputs and workspace are those of rbd_fit.
+ * The errors are downdated as e_j^2 -= 2 t_j (g' x_j) - t_j^2 ||xi||_A^2 with
+ * g = (I - Y Y')(A xi), formed each step, and certified as in rbd_fit.
+ */
+int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const double* weights,
+                     double tol, rbd_tol_mode mode, int32_t d_max, int64_t start,
+                     double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                     int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * rbd_project_workspace_size -- bytes of workspace rbd_project needs.
  */
 int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes);

@@ -86,8 +86,20 @@ def mgs_twice(v: np.ndarray, Y: np.ndarray, d: int) -> np.ndarray:
     return v
 
 
-def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1) -> OracleFit:
-    """Algorithm 1, (Y, T) = RBD(X, eps_R, d_max), with A = I (section 3.1).
+def _anorm_cols(R: np.ndarray, w) -> np.ndarray:
+    """||r_j||_A = sqrt(r_j' A r_j) for A = diag(w) (w = None: the identity)."""
+    if w is None:
+        return _colnorms(R)
+    return np.sqrt(np.einsum("i,ij,ij->j", w, R, R))
+
+
+def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weights=None) -> OracleFit:
+    """Algorithm 1, (Y, T) = RBD(X, eps_R, d_max) (section 3.1).
+
+    ``weights`` = None uses A = I; otherwise A = diag(weights) (the "general
+    diagonal" choice of section 3.2): the basis and T = Y'X are unchanged, and
+    every error of step 2.3 (and E_0, and the relative tolerance) is the
+    A-norm ||x_j - Y T(:, j)||_A of eq. (3), evaluated here by its definition.
 
     ``X`` must already hold the stored values (e.g. FP32- or BF16-rounded data
     upcast to FP64).  Returns the first ``d`` basis vectors, rows of T, pivots,
@@ -103,8 +115,11 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1) -> Or
         raise FloatingPointError("X holds a non-finite value")
     D = min(int(d_max), m, n)
 
-    # pre-computation of diag(X'X): the error of every column with d = 0
-    e = _colnorms(X)
+    w = None if weights is None else np.asarray(weights, dtype=np.float64)
+    if w is not None and (w.shape != (m,) or not np.all(w > 0) or not np.all(np.isfinite(w))):
+        raise ValueError("weights must be m positive finite values")
+    # pre-computation of diag(X'AX): the error of every column with d = 0
+    e = _anorm_cols(X, w)
     E0 = float(e.max())
     tau = float(tol) * E0 if rel else float(tol)
 
@@ -140,7 +155,7 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1) -> Or
         pivots.append(i)
         d += 1
         # 2.3: errors by their definition, pivots masked
-        e = _colnorms(R)
+        e = _anorm_cols(R, w)
         e[chosen] = 0.0
         E_cur = float(e.max())
         gap_hist.append(_gap(e[~chosen], E0) if (~chosen).sum() >= 2 else np.inf)
@@ -152,6 +167,15 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1) -> Or
     return OracleFit(Y=Y[:, :d].copy(), T=T[:d].copy(), pivots=np.array(pivots, dtype=np.int64),
                      col_err=e, err_hist=np.array(err_hist),
                      gap_hist=np.array(gap_hist), d=d, tau=tau, stop=stop)
+
+
+def eq3_error(x, Y, c, weights=None):
+    """eq. (3): ||v - Y c||_A^2 = v'Av - 2 c'Y'Av + c'Y'AYc for A = diag(weights)."""
+    x = np.asarray(x, dtype=np.float64)
+    w = np.ones(x.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64)
+    Av = w * x
+    AY = w[:, None] * Y
+    return float(x @ Av - 2.0 * c @ (Y.T @ Av) + c @ (Y.T @ AY) @ c)
 
 
 def rbd_brute(X, steps: int, start: int = -1):

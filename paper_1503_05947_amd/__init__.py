@@ -88,34 +88,47 @@ class FitBuffers:
                          err_hist=self.err_hist[: d + 1], d=d, stop=STOP_NAMES.get(stop, str(stop)))
 
 
-def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: int = -1, stream=None) -> None:
-    """Enqueue rbd_fit on ``stream`` (default: torch's current stream) without waiting."""
+def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: int = -1, stream=None,
+             weights=None) -> None:
+    """Enqueue rbd_fit (or rbd_fit_weighted when ``weights`` is given: A = diag(weights))
+    on ``stream`` (default: torch's current stream) without waiting."""
     torch = _torch()
     _check_matrix(X, "X")
     if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
         raise ValueError("X does not match the buffers' shape/dtype")
+    if weights is not None:
+        if (weights.dtype != torch.float64 or weights.dim() != 1 or weights.numel() != bufs.m
+                or weights.device != X.device or not weights.is_contiguous()):
+            raise ValueError("weights must be a contiguous float64 vector of m values on X's device")
     lib = load()
     with torch.cuda.device(X.device):
         s = stream if stream is not None else torch.cuda.current_stream(X.device)
         ints = bufs.ints.data_ptr()
-        rc = lib.rbd_fit(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol),
-                         _lib.RBD_TOL_REL if rel else _lib.RBD_TOL_ABS, bufs.d_max, int(start),
-                         bufs.Y.data_ptr(), bufs.T.data_ptr(), bufs.pivots.data_ptr(), bufs.col_err.data_ptr(),
-                         bufs.err_hist.data_ptr(), ints, ints + 4, ints + 8,
-                         bufs.workspace.data_ptr(), bufs.workspace.numel(), s.cuda_stream)
+        mode = _lib.RBD_TOL_REL if rel else _lib.RBD_TOL_ABS
+        outs = (bufs.Y.data_ptr(), bufs.T.data_ptr(), bufs.pivots.data_ptr(), bufs.col_err.data_ptr(),
+                bufs.err_hist.data_ptr(), ints, ints + 4, ints + 8, bufs.workspace.data_ptr(),
+                bufs.workspace.numel(), s.cuda_stream)
+        if weights is None:
+            rc = lib.rbd_fit(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol), mode,
+                             bufs.d_max, int(start), *outs)
+        else:
+            rc = lib.rbd_fit_weighted(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0),
+                                      weights.data_ptr(), float(tol), mode, bufs.d_max, int(start), *outs)
     _lib.check(rc, "rbd_fit")
 
 
-def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1, stream=None) -> FitResult:
+def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1, stream=None,
+        weights=None) -> FitResult:
     """Algorithm 1 on a device matrix X (m x n, f32/bf16/f16/f64 storage).
 
     ``tol`` is eps_R (absolute, or relative to max_j ||x_j|| when ``rel``);
-    ``start < 0`` starts from the column of largest norm.  Waits for the
+    ``start < 0`` starts from the column of largest norm; ``weights`` (float64,
+    m values > 0) selects the diagonal A-norm of section 3.2.  Waits for the
     device and returns views of the first d basis vectors / rows of T.
     """
     torch = _torch()
     bufs = FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
-    fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream)
+    fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream, weights=weights)
     (stream or torch.cuda.current_stream(X.device)).synchronize()
     return bufs.result()
 

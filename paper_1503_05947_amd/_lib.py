@@ -24,6 +24,8 @@ SIGNATURES = {
     "rbd_fit_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_fit": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbd_fit_weighted": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32, _i64,
+                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_project_workspace_size": (ctypes.c_int, [_i64, _i32, _i64, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_project": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, ctypes.c_int, _i64, _i64, _vp, _vp,
                                    _vp, _sz, _vp]),

@@ -50,7 +50,8 @@ struct FitPlan {
     int ntickets = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
-    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_part,
+    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_hw,
+        o_part,
         o_l2, o_rpart, total;
 };
 
@@ -121,10 +122,14 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_v2 = take(8 * m);
     P->o_h2 = take(8 * (size_t)RBD_MAX_D);
     P->o_nu2 = take(8);
-    const size_t part_elems = std::max<size_t>((size_t)P->sc_S * n, (size_t)P->cg_S * std::max(P->D, 1));
+    P->o_g = take(8 * m);
+    P->o_hw = take(8 * (size_t)RBD_MAX_D);
+    // scan partials (two rows of n per slab with a diagonal A-norm); Gram-Schmidt partials
+    const size_t part_elems = std::max<size_t>((size_t)P->sc_S * 2 * n,
+                                               (size_t)P->cg_S * (std::max(P->D, 1) + 2));
     P->o_part = take(8 * part_elems);
     const size_t l2_elems =
-        std::max<size_t>((size_t)P->up_SG * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
+        std::max<size_t>((size_t)P->up_SG * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
     P->o_l2 = take(8 * l2_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * n);
     P->total = o;
@@ -199,12 +204,12 @@ inline void prof_step(hipStream_t s) {
 // or one chunk with 8 rows in flight (2-byte types).
 template <typename Tx, int MODE>
 void launch_xscan(const FitPlan& P, const Tx* X, int64_t ldx, const double* v2, State* st, double* Y, int dcol,
-                  double* part, int vec_ok, bool nt, hipStream_t s) {
+                  double* part, int vec_ok, bool nt, hipStream_t s, const double* g2 = nullptr) {
     const dim3 grid(P.sc_tiles, P.sc_S);
-    const size_t lds = MODE == kScanDot ? sizeof(double) * P.sc_rows : 0;
+    const size_t lds = MODE == kScanSqr ? 0 : sizeof(double) * P.sc_rows * (MODE == kScanDot2 ? 2 : 1);
 #define RBD_XSCAN(U, NT, CH)                                                                                 \
     xscan_kernel<Tx, MODE, U, NT, CH><<<grid, P.sc_tpb, lds, s>>>(X, ldx, P.m, P.n, v2, st, Y, P.d_max, dcol, \
-                                                                  P.sc_rows, part, vec_ok)
+                                                                  P.sc_rows, part, vec_ok, g2)
     if (sizeof(Tx) == 2) {
         if (nt) RBD_XSCAN(8, true, 1);
         else RBD_XSCAN(8, false, 1);
@@ -234,9 +239,19 @@ void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, co
 
 template <int KC>
 void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
-                 double* v2, double* part, hipStream_t s) {
-    cgs2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2,
-                                                                part);
+                 double* v2, double* part, const double* w, hipStream_t s) {
+    if (w)
+        cgs2_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
+                                                                          v2, part, w, std::max(P.D, 1));
+    else
+        cgs2_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
+                                                                           v2, part, nullptr, std::max(P.D, 1));
+}
+
+template <int KC>
+void launch_gvec(const FitPlan& P, const double* Y, const State* st, int d, const double* v2, const double* w,
+                 const double* hw, double* g, hipStream_t s) {
+    gvec_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v2, w, hw, g);
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
@@ -252,7 +267,7 @@ void launch_sum_rows(const State* st, const double* part, int64_t ldp, int rows,
 template <typename Tx>
 int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, int64_t start, double* Y,
               double* T, int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
-              int32_t* stop_reason, char* ws, hipStream_t s) {
+              int32_t* stop_reason, char* ws, hipStream_t s, const double* w) {
     State* st = reinterpret_cast<State*>(ws + P.o_state);
     unsigned* tickets = reinterpret_cast<unsigned*>(ws + P.o_tickets);
     double* e2 = reinterpret_cast<double*>(ws + P.o_e2);
@@ -267,6 +282,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     double* part = reinterpret_cast<double*>(ws + P.o_part);
     double* l2 = reinterpret_cast<double*>(ws + P.o_l2);
     double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
+    double* g = reinterpret_cast<double*>(ws + P.o_g);
+    double* hw = reinterpret_cast<double*>(ws + P.o_hw);
+    const bool W = (w != nullptr);
+    const int64_t nw = W ? 2 * P.n : P.n;     // scan partial row length
 
     const int N = Ld<Tx>::N;
     const int vec_ok = (ldx % N == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
@@ -279,12 +298,14 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     RBD_LAUNCH_CHECK();
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
     prof_begin(RBD_PHASE_COLNORM, s);
-    launch_xscan<Tx, kScanSqr>(P, X, ldx, nullptr, st, Y, 0, part, vec_ok, nt, s);
+    if (W) launch_xscan<Tx, kScanSqrW>(P, X, ldx, w, st, Y, 0, part, vec_ok, nt, s);
+    else launch_xscan<Tx, kScanSqr>(P, X, ldx, nullptr, st, Y, 0, part, vec_ok, nt, s);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_COLNORM, s);
     prof_begin(RBD_PHASE_INIT, s);
     const int up_per = (int)cdiv(P.sc_S, P.up_SG);
     const dim3 red_grid((unsigned)cdiv(P.n, 256), (unsigned)cdiv(P.sc_S, up_per));
+    const dim3 red_grid_step((unsigned)cdiv(nw, 256), (unsigned)cdiv(P.sc_S, up_per));
     const int up_groups = (int)cdiv(P.sc_S, up_per);
     reduce_rows_kernel<<<red_grid, 256, 0, s>>>(nullptr, part, P.n, P.sc_S, up_per, P.n, l2, P.n);
     RBD_LAUNCH_CHECK();
@@ -310,30 +331,51 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
         switch (kc_for(d)) {
-            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, s); break;
-            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, w, s); break;
+            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, w, s); break;
+            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, w, s); break;
+            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, w, s); break;
+            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, w, s); break;
         }
         RBD_LAUNCH_CHECK();
-        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S);
+        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S, W ? 1 : 0);
         RBD_LAUNCH_CHECK();
+        if (W) {
+            // g = P_d(A xi): hw = Y'(w . v2) from cgs2's partials, then g
+            if (d > 0) {
+                launch_sum_rows(st, part + 2 * (int64_t)P.cg_S, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, hw, 0,
+                                s);
+                RBD_LAUNCH_CHECK();
+            }
+            switch (kc_for(d)) {
+                case 1: launch_gvec<1>(P, Y, st, d, v2, w, hw, g, s); break;
+                case 2: launch_gvec<2>(P, Y, st, d, v2, w, hw, g, s); break;
+                case 4: launch_gvec<4>(P, Y, st, d, v2, w, hw, g, s); break;
+                case 8: launch_gvec<8>(P, Y, st, d, v2, w, hw, g, s); break;
+                default: launch_gvec<16>(P, Y, st, d, v2, w, hw, g, s); break;
+            }
+            RBD_LAUNCH_CHECK();
+        }
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
-        launch_xscan<Tx, kScanDot>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s);
+        if (W) launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s, g);
+        else launch_xscan<Tx, kScanDot>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_XSCAN, s);
         prof_begin(RBD_PHASE_UPDATE, s);
-        reduce_rows_kernel<<<red_grid, 256, 0, s>>>(st, part, P.n, P.sc_S, up_per, P.n, l2, P.n);
+        reduce_rows_kernel<<<red_grid_step, 256, 0, s>>>(st, part, nw, P.sc_S, up_per, nw, l2, nw);
         RBD_LAUNCH_CHECK();
-        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
-                                                      flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        if (W)
+            update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
+                                                           flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        else
+            update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
+                                                          flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
         resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
-                                                    P.rc_rows, P.rc_S, rpart, P.n);
+                                                    P.rc_rows, P.rc_S, rpart, P.n, w);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID, s);
         prof_begin(RBD_PHASE_RESID_FINISH, s);
@@ -394,7 +436,7 @@ int project_typed(const ProjPlan& P, const double* Y, int64_t ldy, int64_t m, in
     sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(len, 256)), 256, 0, s>>>(part, P.S, len, Tv_out, 0);
     RBD_LAUNCH_CHECK();
     resid_kernel<Tv><<<P.rc_grid, 256, 0, s>>>(V, ldv, m, Y, ldy, d, Tv_out, k, nullptr, nullptr, (int)k, P.rc_rows,
-                                               P.rc_S, rpart, k);
+                                               P.rc_S, rpart, k, nullptr);
     RBD_LAUNCH_CHECK();
     sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(k, 256)), 256, 0, s>>>(rpart, P.rc_S, k, err_v, 1);
     RBD_LAUNCH_CHECK();
@@ -416,10 +458,10 @@ int rbd_fit_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, si
     return RBD_OK;
 }
 
-int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
-            int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
-            int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace, size_t workspace_bytes,
-            void* stream) {
+static int fit_entry(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
+                     int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err,
+                     double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace,
+                     size_t workspace_bytes, void* stream, const double* w) {
     FitPlan P;
     if (!make_fit_plan(m, n, d_max, xt, &P)) return RBD_EINVAL;
     if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status || !workspace) return RBD_EINVAL;
@@ -435,18 +477,35 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, doub
     switch (xt) {
         case RBD_F32:
             return fit_typed<float>(P, static_cast<const float*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
-                                    err_hist, d_out, status, stop_reason, ws, s);
+                                    err_hist, d_out, status, stop_reason, ws, s, w);
         case RBD_F64:
             return fit_typed<double>(P, static_cast<const double*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
-                                     err_hist, d_out, status, stop_reason, ws, s);
+                                     err_hist, d_out, status, stop_reason, ws, s, w);
         case RBD_BF16:
             return fit_typed<bf16_t>(P, static_cast<const bf16_t*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
-                                     err_hist, d_out, status, stop_reason, ws, s);
+                                     err_hist, d_out, status, stop_reason, ws, s, w);
         case RBD_F16:
             return fit_typed<f16_t>(P, static_cast<const f16_t*>(X), ldx, tol, rel, start, Y, T, pivots, col_err,
-                                    err_hist, d_out, status, stop_reason, ws, s);
+                                    err_hist, d_out, status, stop_reason, ws, s, w);
     }
     return RBD_EINVAL;
+}
+
+int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
+            int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+            int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace, size_t workspace_bytes,
+            void* stream) {
+    return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
+                     stop_reason, workspace, workspace_bytes, stream, nullptr);
+}
+
+int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const double* weights,
+                     double tol, rbd_tol_mode mode, int32_t d_max, int64_t start, double* Y, double* T,
+                     int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
+                     int32_t* stop_reason, void* workspace, size_t workspace_bytes, void* stream) {
+    if (!weights) return RBD_EINVAL;
+    return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
+                     stop_reason, workspace, workspace_bytes, stream, weights);
 }
 
 int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes) {

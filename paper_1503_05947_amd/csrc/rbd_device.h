@@ -34,6 +34,8 @@ struct State {
     double E0;      // max_j ||x_j||
     double nu;      // ||v|| after the second Gram-Schmidt pass
     double inv_nu;  // 1 / nu
+    double wxx;     // ||xi||_A^2 = sum_i w_i xi_i^2 (diagonal A only)
+    double pad1;
 };
 
 // ---------------------------------------------------------------------------

@@ -29,7 +29,11 @@
 namespace rbd {
 
 
-enum { kScanDot = 0, kScanSqr = 1 };
+// kScanDot:  acc_j = sum_i xi_i x_ij            (xi = v2 / nu)
+// kScanSqr:  acc_j = sum_i x_ij^2
+// kScanSqrW: acc_j = sum_i w_i x_ij^2            (diagonal A; w passed as v2)
+// kScanDot2: acc_j = sum_i xi_i x_ij and acc2_j = sum_i g_i x_ij (diagonal A)
+enum { kScanDot = 0, kScanSqr = 1, kScanSqrW = 2, kScanDot2 = 3 };
 
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void finish_step(State* st, int d, double vmax, int64_t imax,
@@ -52,7 +56,7 @@ __global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, in
     if (gid == 0) {
         st->d = 0; st->p = 0; st->stop = 0; st->status = RBD_OK; st->nflag = 0; st->D = D;
         st->nonfinite = 0; st->pad0 = 0;
-        st->tau = 0.0; st->E0 = 0.0; st->nu = 0.0; st->inv_nu = 0.0;
+        st->tau = 0.0; st->E0 = 0.0; st->nu = 0.0; st->inv_nu = 0.0; st->wxx = 0.0; st->pad1 = 0.0;
     }
 }
 
@@ -68,22 +72,27 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
                                                      int64_t n, const double* __restrict__ v2,
                                                      State* __restrict__ st, double* __restrict__ Y,
                                                      int64_t ldy, int dcol, int rows_per_slab,
-                                                     double* __restrict__ part, int vec_ok) {
-    if (MODE == kScanDot && st->stop) return;
+                                                     double* __restrict__ part, int vec_ok,
+                                                     const double* __restrict__ g2) {
+    constexpr bool DOT = (MODE == kScanDot || MODE == kScanDot2);
+    constexpr bool TWO = (MODE == kScanDot2);
+    constexpr bool WTS = (MODE != kScanSqr);       // a per-row weight is staged in LDS
+    if (DOT && st->stop) return;
     using L = Ld<Tx>;
     using R = typename L::raw;
     constexpr int N = L::N;
-    extern __shared__ double xi_s[];
+    extern __shared__ double xi_s[];               // rows_per_slab (x2 for kScanDot2)
     const int tile = blockIdx.x, slab = blockIdx.y;
     const int64_t r0 = (int64_t)slab * rows_per_slab;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_slab);
     const int nr = (int)(r1 - r0);
-    if (MODE == kScanDot) {
-        const double inv = st->inv_nu;
+    if (WTS) {
+        const double inv = DOT ? st->inv_nu : 1.0;
         for (int r = threadIdx.x; r < nr; r += blockDim.x) {
             const double xi = v2[r0 + r] * inv;
             xi_s[r] = xi;
-            if (tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
+            if (TWO) xi_s[rows_per_slab + r] = g2[r0 + r];
+            if (DOT && tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
         }
         __syncthreads();
     }
@@ -99,10 +108,24 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
         full[q] = vec_ok && ncols[q] == N;
     }
     double acc[CH][N];
+    double acc2[TWO ? CH : 1][N];
 #pragma unroll
     for (int q = 0; q < CH; ++q)
 #pragma unroll
         for (int e = 0; e < N; ++e) acc[q][e] = 0.0;
+#pragma unroll
+    for (int q = 0; q < (TWO ? CH : 1); ++q)
+#pragma unroll
+        for (int e = 0; e < N; ++e) acc2[q][e] = 0.0;
+    auto fold = [&](int q, const double* x, double w, double g) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            if (MODE == kScanSqr) acc[q][e] = fma(x[e], x[e], acc[q][e]);
+            else if (MODE == kScanSqrW) acc[q][e] = fma(w * x[e], x[e], acc[q][e]);
+            else acc[q][e] = fma(w, x[e], acc[q][e]);
+            if (TWO) acc2[TWO ? q : 0][e] = fma(g, x[e], acc2[TWO ? q : 0][e]);
+        }
+    };
     const Tx* p = X + r0 * ldx + cbase;
     int r = 0;
     for (; r + U <= nr; r += U) {
@@ -117,7 +140,8 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
                 }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double w = (MODE == kScanDot) ? xi_s[r + u] : 0.0;
+            const double w = WTS ? xi_s[r + u] : 0.0;
+            const double g = TWO ? xi_s[rows_per_slab + r + u] : 0.0;
 #pragma unroll
             for (int q = 0; q < CH; ++q) {
                 double x[N];
@@ -128,14 +152,13 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
                     for (int e = 0; e < N; ++e)
                         x[e] = e < ncols[q] ? L::one(p + (int64_t)(r + u) * ldx + q * cstep + e) : 0.0;
                 }
-#pragma unroll
-                for (int e = 0; e < N; ++e)
-                    acc[q][e] = (MODE == kScanDot) ? fma(w, x[e], acc[q][e]) : fma(x[e], x[e], acc[q][e]);
+                fold(q, x, w, g);
             }
         }
     }
     for (; r < nr; ++r) {
-        const double w = (MODE == kScanDot) ? xi_s[r] : 0.0;
+        const double w = WTS ? xi_s[r] : 0.0;
+        const double g = TWO ? xi_s[rows_per_slab + r] : 0.0;
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
             double x[N];
@@ -145,15 +168,18 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
 #pragma unroll
                 for (int e = 0; e < N; ++e) x[e] = e < ncols[q] ? L::one(p + (int64_t)r * ldx + q * cstep + e) : 0.0;
             }
-#pragma unroll
-            for (int e = 0; e < N; ++e)
-                acc[q][e] = (MODE == kScanDot) ? fma(w, x[e], acc[q][e]) : fma(x[e], x[e], acc[q][e]);
+            fold(q, x, w, g);
         }
     }
+    // partial rows: n values (acc), then n more (acc2) for kScanDot2
+    const int64_t ldp = TWO ? 2 * n : n;
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
-        double* out = part + (int64_t)slab * n + cbase + q * cstep;
-        for (int e = 0; e < ncols[q]; ++e) out[e] = acc[q][e];
+        double* out = part + (int64_t)slab * ldp + cbase + q * cstep;
+        for (int e = 0; e < ncols[q]; ++e) {
+            out[e] = acc[q][e];
+            if (TWO) out[n + e] = acc2[TWO ? q : 0][e];
+        }
     }
 }
 
@@ -163,7 +189,9 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
 // lowest-index argmax.  One block per 256 columns; the last block to arrive
 // combines the block maxima and closes the step.
 // ---------------------------------------------------------------------------
-enum { kInit = 0, kStep = 1 };
+// kStepW: diagonal A; l2 rows hold t_j (first n) and s_j = g' x_j (next n), and
+// e_j^2 -= 2 t_j s_j - t_j^2 ||xi||_A^2.
+enum { kInit = 0, kStep = 1, kStepW = 2 };
 
 template <int MODE>
 __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restrict__ st, int d,
@@ -175,17 +203,19 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
                                                       double* __restrict__ bres_v, int64_t* __restrict__ bres_i,
                                                       int64_t* __restrict__ pivots, double* __restrict__ err_hist,
                                                       int64_t start, double tol, int rel) {
-    if (MODE == kStep && st->stop) return;
+    constexpr bool STEP = (MODE != kInit);
+    if (STEP && st->stop) return;
     __shared__ double sv[4];
     __shared__ int64_t si[4];
     const int cb = blockIdx.x, ncb = gridDim.x;
+    const int64_t ldl = (MODE == kStepW) ? 2 * n : n;
     const int64_t j = (int64_t)cb * blockDim.x + threadIdx.x;
 
     double best = -1.0;
     int64_t bi = INT64_MAX;
     if (j < n) {
         double t = 0.0;
-        for (int q = 0; q < SG; ++q) t += l2[(int64_t)q * n + j];
+        for (int q = 0; q < SG; ++q) t += l2[(int64_t)q * ldl + j];
         double e;
         if (MODE == kInit) {
             e = t;
@@ -194,7 +224,13 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
             if (!isfinite(e)) atomicOr(&st->nonfinite, 1);
         } else {
             T[(int64_t)d * ldt + j] = t;
-            e = e2[j] - t * t;
+            if (MODE == kStepW) {
+                double sj = 0.0;
+                for (int q = 0; q < SG; ++q) sj += l2[(int64_t)q * ldl + n + j];
+                e = e2[j] - (2.0 * t * sj - t * t * st->wxx);
+            } else {
+                e = e2[j] - t * t;
+            }
             if (!(e > 0.0)) e = 0.0;
             double b = base2[j];
             if (j == (int64_t)st->p) {
@@ -213,7 +249,7 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
     block_argmax(best, bi, sv, si);
     if (threadIdx.x == 0) { bres_v[cb] = best; bres_i[cb] = bi; }
     if (!last_to_arrive(&tickets[ncb], (unsigned)ncb)) return;
-    if (MODE == kStep && __hip_atomic_load(&st->nflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+    if (STEP && __hip_atomic_load(&st->nflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
         // list the queued columns in ascending order (so neighbouring columns
         // share the cache lines of X) and clear their flags
         __shared__ int scan[256];
@@ -331,29 +367,41 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int
 // ---------------------------------------------------------------------------
 // cgs2: v2 = v1 - Y(:, 0:d) h2, nu = ||v2||, and step 2.2's break test.
 // ---------------------------------------------------------------------------
-template <int KC, int RU>
+template <int KC, int RU, bool W>
 __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
                                                     State* __restrict__ st, int d, int rows_per_blk,
                                                     const double* __restrict__ v1, const double* __restrict__ h2,
-                                                    double* __restrict__ v2, double* __restrict__ part) {
+                                                    double* __restrict__ v2, double* __restrict__ part,
+                                                    const double* __restrict__ w, int64_t ldp) {
+    // part[blk] = sum ||v2||^2; with W also part[S + blk] = sum w v2^2 and
+    // part[2S + blk*ldp + k] = sum_i Y[i,k] w_i v2_i   (S = gridDim.x)
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
+    __shared__ double accs[W ? KW : 1];
     __shared__ double sred[4];
-    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? h2[k] : 0.0;
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? h2[k] : 0.0;
+        if (W) accs[k] = 0.0;
+    }
     __syncthreads();
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
-    double nacc = 0.0;
-    for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+    double nacc = 0.0, wacc = 0.0;
+    double hacc[W ? KC : 1];
+#pragma unroll
+    for (int c = 0; c < (W ? KC : 1); ++c) hacc[c] = 0.0;
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
         double y[RU][KC];
         double vv[RU];
+        double wr[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t r = rb + u;
             const bool ok = r < r1;
             vv[u] = ok ? v1[r] : 0.0;
+            wr[u] = (W && ok) ? w[r] : 0.0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
@@ -371,31 +419,106 @@ __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y,
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const double v = vv[u] - dot[u];
+            if (W) {
+                const double wv2 = wr[u] * v;            // rows past the end have w = 0
+#pragma unroll
+                for (int c = 0; c < KC; ++c) hacc[W ? c : 0] = fma(y[u][c], wv2, hacc[W ? c : 0]);
+            }
             if (lane == u && rb + u < r1) {
                 v2[rb + u] = v;
                 nacc = fma(v, v, nacc);
+                if (W) wacc = fma(wr[u] * v, v, wacc);
             }
         }
     }
     const double s = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+    if (W) {
+        const double sw = block_sum(wacc, sred);
+        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = sw;
+        if (d > 0) {
+            for (int q = 0; q < nw; ++q) {
+                if (wv == q) {
+#pragma unroll
+                    for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += hacc[W ? c : 0];
+                }
+                __syncthreads();
+            }
+            double* ph = part + 2 * (int64_t)gridDim.x + (int64_t)blockIdx.x * ldp;
+            for (int k = threadIdx.x; k < d; k += blockDim.x) ph[k] = accs[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gvec (diagonal A): g = (w . v2 - Y hw) / nu, hw = Y'(w . v2), i.e.
+// g = P_{d}(A xi) with P_d the projector onto the complement of span(Y).
+// Then g' x_j drives the weighted downdate of the errors.
+// ---------------------------------------------------------------------------
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                    const State* __restrict__ st, int d, int rows_per_blk,
+                                                    const double* __restrict__ v2, const double* __restrict__ w,
+                                                    const double* __restrict__ hw, double* __restrict__ g) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? hw[k] : 0.0;
+    __syncthreads();
+    const double inv = st->inv_nu;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+        double dot[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            dot[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
+        }
+        wave_sum_n<RU>(dot);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (lane == u && rb + u < r1) g[rb + u] = (w[rb + u] * v2[rb + u] - dot[u]) * inv;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // nu: nu = ||v2|| from the cgs2 partials (one block, fixed order) and step
 // 2.2's test: ||v|| < eps_R (or ||v|| = 0) keeps the d vectors found so far.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S) {
+__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S,
+                                                  int weighted) {
     if (st->stop) return;
     __shared__ double sred[4];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < S; i += blockDim.x) s += part[i];
+    double s = 0.0, sw = 0.0;
+    for (int i = threadIdx.x; i < S; i += blockDim.x) {
+        s += part[i];
+        if (weighted) sw += part[S + i];
+    }
     s = block_sum(s, sred);
+    if (weighted) sw = block_sum(sw, sred);
     if (threadIdx.x == 0) {
         const double nu = sqrt(s);
         st->nu = nu;
-        if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
-        else st->inv_nu = 1.0 / nu;
+        if (nu < st->tau || nu == 0.0) {
+            st->stop = RBD_STOP_BREAK;
+        } else {
+            st->inv_nu = 1.0 / nu;
+            st->wxx = weighted ? sw / s : 0.0;     // ||v2||_A^2 / ||v2||^2 = ||xi||_A^2
+        }
     }
 }
 
@@ -433,7 +556,8 @@ __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, in
                                                      const double* __restrict__ C, int64_t ldc,
                                                      const int* __restrict__ J, const int* __restrict__ count_dev,
                                                      int count_host, int rows_per_slab, int nslab,
-                                                     double* __restrict__ part, int64_t ldp) {
+                                                     double* __restrict__ part, int64_t ldp,
+                                                     const double* __restrict__ w) {
     const int cnt = count_dev ? *count_dev : count_host;
     if (cnt == 0) return;
     constexpr int TM = 128, TN = 64, KB = 16;
@@ -502,7 +626,7 @@ __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, in
                     const int col = cols[tx + 16 * b];
                     if (row < rend && col >= 0) {
                         const double r = Ld<Tx>::one(X + row * ldx + col) - acc[a][b];
-                        rs[b] = fma(r, r, rs[b]);
+                        rs[b] = w ? fma(w[row] * r, r, rs[b]) : fma(r, r, rs[b]);
                     }
                 }
             }

@@ -329,3 +329,27 @@ def batched_matrix(seed: int, index: int, m: int, n: int, decade: float = 8.0) -
 
 def cotangent(seed: int, m: int, n: int) -> np.ndarray:
     return rng(5, seed, S_G).standard_normal((m, n))
+
+
+# ----------------------------------------------------------------------------
+# diagonal A-norm weights (section 3.2, "general diagonal matrix")
+# ----------------------------------------------------------------------------
+
+def band_weights(m: int, start: float = 0.25, stop: float = 0.5, hi: float = 100.0, lo: float = 1.0) -> np.ndarray:
+    """Rows start*m .. stop*m (a band of the spatial grid) weighted hi, the rest lo."""
+    w = np.full(m, float(lo))
+    w[int(start * m):int(stop * m)] = float(hi)
+    return w
+
+
+def random_weights(seed: int, m: int, lo: float = 0.1, hi: float = 10.0) -> np.ndarray:
+    """Log-uniform weights in [lo, hi]."""
+    g = rng(6, seed, S_G)
+    return np.exp(g.uniform(math.log(lo), math.log(hi), size=m))
+
+
+def disc_weights(grid: int, centre=(0.5, 0.5), radius: float = 0.25, hi: float = 100.0) -> np.ndarray:
+    """Rows of a grid x grid field (row = grid*a + b) inside a disc weighted hi, the rest 1."""
+    s = np.arange(grid, dtype=np.float64) / max(grid - 1, 1)
+    inside = ((s[:, None] - centre[0]) ** 2 + (s[None, :] - centre[1]) ** 2) <= radius * radius
+    return np.where(inside, float(hi), 1.0).reshape(-1)

@@ -21,8 +21,9 @@ def separated_prefix(ref, gap: float) -> int:
     return ref.d
 
 
-def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: bool = True):
-    """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values."""
+def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: bool = True, weights=None):
+    """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values;
+    weights: the diagonal of A when the errors are A-norms (eq. (3)), else None."""
     msgs = []
     E0 = ref.err_hist[0]
     k = min(separated_prefix(ref, gap), dev["d"], ref.d)
@@ -53,32 +54,39 @@ def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: boo
         msgs.append(f"d differs after a fully separated run: {dev['d']} vs {ref.d}")
     if dev["d"] == ref.d and abs(dev["err_hist"][dev["d"]] - ref.err_hist[ref.d]) > rtol * E0:
         msgs.append("final error differs: %.6e vs %.6e" % (dev["err_hist"][dev["d"]], ref.err_hist[ref.d]))
-    msgs += invariant_msgs(dev, X, rtol)
+    msgs += invariant_msgs(dev, X, rtol, weights=weights)
     return msgs
 
 
-def invariant_msgs(dev, X, rtol=1e-5):
-    """Checks a device fit on its own: orthonormal Y, T = Y'X, certified errors, monotone history."""
+def _norms(R, weights):
+    if weights is None:
+        return np.linalg.norm(R, axis=0)
+    return np.sqrt(np.asarray(weights, dtype=np.float64) @ (R * R))
+
+
+def invariant_msgs(dev, X, rtol=1e-5, weights=None):
+    """Checks a device fit on its own: orthonormal Y, T = Y'X, certified errors, monotone history
+    (with A = I: a Euclidean projection residual can grow in another A-norm)."""
     msgs = []
     d = dev["d"]
     Y, T = dev["Y"][:, :d], dev["T"][:d]
     nx = np.linalg.norm(X, axis=0)
-    E0 = nx.max()
+    E0 = _norms(X, weights).max()
     if d:
         o = np.max(np.abs(Y.T @ Y - np.eye(d)))
         if o > 1e-12:
             msgs.append(f"Y not orthonormal ({o:.2e})")
         dt = np.max(np.abs(T - Y.T @ X))
-        if dt > 1e-12 * max(E0, 1e-300) * np.sqrt(X.shape[0]):
+        if dt > 1e-12 * max(nx.max(), 1e-300) * np.sqrt(X.shape[0]):
             msgs.append(f"T != Y'X ({dt:.2e})")
-    true_err = np.linalg.norm(X - Y @ T, axis=0)
+    true_err = _norms(X - Y @ T, weights)
     if d:
         true_err[dev["pivots"][:d]] = 0.0
     de = np.max(np.abs(true_err - dev["col_err"]))
     if de > rtol * max(E0, 1e-300):
         msgs.append(f"col_err not the true residual norm ({de / max(E0, 1e-300):.2e} E0)")
     h = dev["err_hist"][: d + 1]
-    if np.any(np.diff(h) > 1e-9 * max(E0, 1e-300)):
+    if weights is None and np.any(np.diff(h) > 1e-9 * max(E0, 1e-300)):
         msgs.append("error history increases")
     if len(set(dev["pivots"][:d].tolist())) != d:
         msgs.append("repeated pivot")

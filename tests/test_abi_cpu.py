@@ -153,3 +153,14 @@ def test_batch_plan_offsets_and_order(lib):
                               ctypes.byref(sizes)) == _lib.RBD_EINVAL
     assert lib.rbd_batch_plan(ms.ctypes.data, ns.ctypes.data, 4, 300, desc.ctypes.data, order.ctypes.data,
                               ctypes.byref(sizes)) == _lib.RBD_EINVAL
+
+
+def test_weighted_fit_rejects_missing_weights(lib):
+    from paper_1503_05947_amd import _lib
+    fake = ctypes.c_void_p(4096)
+    rc = lib.rbd_fit_weighted(fake, 0, 10, 10, 10, None, 0.0, 0, 5, -1, fake, fake, fake, fake, fake, fake, fake,
+                              None, ctypes.c_void_p(1 << 20), 1 << 30, None)
+    assert rc == _lib.RBD_EINVAL
+    rc = lib.rbd_fit_weighted(fake, 0, 10, 10, 9, fake, 0.0, 0, 5, -1, fake, fake, fake, fake, fake, fake, fake,
+                              None, ctypes.c_void_p(1 << 20), 1 << 30, None)
+    assert rc == _lib.RBD_EINVAL      # ldx < n

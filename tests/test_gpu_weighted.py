@@ -1,0 +1,121 @@
+"""Parity of rbd_fit_weighted (A = diag(w), section 3.2 and eq. (3)) with the FP64 oracle.
+
+The oracle evaluates every A-norm error by its definition on the explicit
+residual; the device downdates them and certifies them by exact refreshes.
+Every case prints its name, shape and seed before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_fit
+from test_gpu_fit import to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def run(stored, dtype, w, tol, d_max, rel=False, start=-1, pad_cols=0):
+    import torch
+    import paper_1503_05947_amd as rbd
+    X = to_device(stored, dtype, pad_cols)
+    wd = None if w is None else torch.from_numpy(np.ascontiguousarray(w, dtype=np.float64)).to("cuda:0")
+    res = rbd.fit(X, tol=tol, d_max=d_max, rel=rel, start=start, weights=wd)
+    return dict(Y=res.Y.cpu().numpy(), T=res.T.cpu().numpy(), pivots=res.pivots.cpu().numpy(),
+                col_err=res.col_err.cpu().numpy(), err_hist=res.err_hist.cpu().numpy(), d=res.d,
+                stop=res.stop)
+
+
+def check(name, stored, vals, dtype, w, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-6):
+    print(f"[gpu] weighted {name} dtype={dtype} shape={vals.shape} tol={tol} rel={rel} d_max={d_max}",
+          flush=True)
+    dev = run(stored, dtype, w, tol, d_max, rel=rel, start=start, pad_cols=pad_cols)
+    ref = oracle.rbd_fit(vals, tol, d_max, rel=rel, start=start, weights=w)
+    msgs = compare_fit(dev, ref, vals, gap=gap, weights=w)
+    assert msgs == [], f"{name}: " + "; ".join(msgs)
+    return dev, ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lowrank_random_weights(dtype, seed):
+    wl = synth.lowrank_spectrum(seed)
+    stored, vals = synth.quantize(wl.X, dtype)
+    w = synth.random_weights(seed, vals.shape[0])
+    dev, ref = check(f"lowrank seed={seed}", stored, vals, dtype, w, wl.tol, wl.d_max)
+    if dtype == "f64":
+        assert dev["d"] == ref.d and np.array_equal(dev["pivots"], ref.pivots)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_bump_field_band_weights(dtype):
+    """Rows of one band of the grid weighted 100x: relative tol 1e-4, d_max 256."""
+    wl = synth.bump_field(0)
+    stored, vals = synth.quantize(wl.X, dtype)
+    w = synth.band_weights(vals.shape[0])
+    check("bump band", stored, vals, dtype, w, wl.tol, wl.d_max, rel=True)
+
+
+def test_ragged_shape_padded_rows():
+    """m, n not multiples of any tile; ldx > n; tol 0 runs to d_max."""
+    X = synth.random_rank(3, 1000, 777, 60)
+    stored, vals = synth.quantize(X, "f32")
+    w = synth.random_weights(3, 1000)
+    dev, ref = check("ragged", stored, vals, "f32", w, 0.0, 50, pad_cols=5)
+    assert dev["d"] == ref.d == 50
+
+
+def test_start_column_and_absolute_tol():
+    wl = synth.lowrank_spectrum(2)
+    stored, vals = synth.quantize(wl.X, "f64")
+    w = synth.random_weights(7, vals.shape[0])
+    dev, ref = check("start=17", stored, vals, "f64", w, 1e-6, 64, start=17)
+    assert dev["pivots"][0] == 17 and dev["d"] == ref.d
+
+
+def test_unit_weights_match_the_identity_path():
+    """A = I through the weighted kernels: same pivots and errors as rbd_fit."""
+    wl = synth.lowrank_spectrum(1)
+    stored, vals = synth.quantize(wl.X, "f32")
+    print("[gpu] weighted unit weights vs identity", flush=True)
+    a = run(stored, "f32", None, wl.tol, wl.d_max)
+    b = run(stored, "f32", np.ones(vals.shape[0]), wl.tol, wl.d_max)
+    assert a["d"] == b["d"] and np.array_equal(a["pivots"][:a["d"]], b["pivots"][:b["d"]])
+    E0 = a["err_hist"][0]
+    assert np.max(np.abs(a["err_hist"][: a["d"] + 1] - b["err_hist"][: b["d"] + 1])) < 1e-9 * E0
+    assert np.max(np.abs(a["Y"][:, :a["d"]] - b["Y"][:, :b["d"]])) < 1e-9
+
+
+def test_constant_weights_scale_errors():
+    """A = c^2 I: same basis, every error times c."""
+    wl = synth.bump_field(1, m=600, n=500)
+    stored, vals = synth.quantize(wl.X, "f64")
+    print("[gpu] weighted constant weights", flush=True)
+    a = run(stored, "f64", None, 0.0, 40)
+    b = run(stored, "f64", np.full(600, 9.0), 0.0, 40)
+    assert np.array_equal(a["pivots"], b["pivots"])
+    assert np.max(np.abs(3.0 * a["err_hist"] - b["err_hist"])) < 1e-9 * b["err_hist"][0]
+
+
+def test_weights_move_the_first_pivot():
+    """Weight on the rows where a small column lives makes it the first pick, as in the oracle."""
+    X = np.zeros((300, 40))
+    g = synth.rng(82, 0, 0)
+    X[:150] = g.standard_normal((150, 40))
+    X[150:, 39] = 0.3
+    w = np.ones(300)
+    w[150:] = 1e4
+    stored, vals = synth.quantize(X, "f64")
+    dev, ref = check("first pivot", stored, vals, "f64", w, 0.0, 10)
+    assert ref.pivots[0] == 39 and dev["pivots"][0] == 39
+
+
+def test_weights_validated_by_the_binding():
+    import torch
+    import paper_1503_05947_amd as rbd
+    print("[gpu] weighted argument checks", flush=True)
+    X = torch.zeros((64, 32), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(ValueError):
+        rbd.fit(X, d_max=4, weights=torch.ones(64, dtype=torch.float32, device="cuda:0"))
+    with pytest.raises(ValueError):
+        rbd.fit(X, d_max=4, weights=torch.ones(63, dtype=torch.float64, device="cuda:0"))
