@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--backward", action="store_true",
                     help="also time the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
                          "fixed from a tol-0 fit, G ~ N(0,1)")
+    ap.add_argument("--weighted", action="store_true",
+                    help="also time the diagonal A-norm fit (disc of rows weighted 100x) on the FP32 field")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one elementwise kernel over 1 GiB (read 1 GiB, write 1 GiB) before the fits, "
                          "as the reference for hardware traffic counters")
@@ -90,17 +92,17 @@ def ensure_built():
         _build.build_library()
 
 
-def time_fits(rbd, X, d_max, K, W):
+def time_fits(rbd, X, d_max, K, W, weights=None):
     import torch
     from paper_1503_05947_amd import _lib
     bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
     for _ in range(W):
-        rbd.fit_into(bufs, X, tol=0.0)
+        rbd.fit_into(bufs, X, tol=0.0, weights=weights)
     torch.cuda.synchronize()
     with _lib.Profiler(phases=("xscan",), max_steps=d_max) as prof:
         t0 = time.perf_counter()
         for _ in range(K):
-            rbd.fit_into(bufs, X, tol=0.0)
+            rbd.fit_into(bufs, X, tol=0.0, weights=weights)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     res = bufs.result()
@@ -108,13 +110,13 @@ def time_fits(rbd, X, d_max, K, W):
                 xscan_launches=prof.launches["xscan"], step_end_ms=list(prof.step_end_ms), bufs=bufs, res=res)
 
 
-def phase_breakdown(rbd, X, d_max):
+def phase_breakdown(rbd, X, d_max, weights=None):
     import torch
     from paper_1503_05947_amd import _lib
     bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
     torch.cuda.synchronize()
     with _lib.Profiler(max_steps=d_max) as prof:
-        rbd.fit_into(bufs, X, tol=0.0)
+        rbd.fit_into(bufs, X, tol=0.0, weights=weights)
     torch.cuda.synchronize()
     return {p: dict(ms=round(prof.phase_ms[p], 4), launches=prof.launches[p],
                     avg_us=round(1e3 * prof.avg_ms(p), 3)) for p in _lib.PHASES}
@@ -453,6 +455,20 @@ def main():
                                "xscan_GBs": round(gbs16, 1), "xscan_frac": round(gbs16 / PEAK_HBM_GBS, 4),
                                "traffic": measured_traffic("bf16", m, n), "algorithmic_bytes": m * n * 2,
                                "kernel_avg_ms": round(runs["bf16"]["xscan_ms"], 4)}
+    if args.weighted:
+        w64 = torch.from_numpy(synth.disc_weights(args.grid)).to(dev)
+        log("diagonal A-norm (disc weights), FP32 storage")
+        rw = time_fits(rbd, X32, args.d_max, args.steps, args.warmup, weights=w64)
+        secw, gbsw = summary(rw, 4)
+        out["weighted"] = {"A": f"diag: rows in a disc of radius 0.25 about (0.5, 0.5) weighted 100, others 1",
+                           "value": round(rw["d"] / secw, 3), "unit": "greedy steps/s",
+                           "ms_per_fit": round(secw * 1e3, 3), "greedy_steps_per_fit": rw["d"],
+                           "xscan_GBs": round(gbsw, 1), "xscan_frac": round(gbsw / PEAK_HBM_GBS, 4),
+                           "algorithmic_bytes": m * n * 4, "kernel_avg_ms": round(rw["xscan_ms"], 4),
+                           "cost_vs_identity": round(secw / sec32, 3)}
+        if args.phases:
+            out["weighted"]["phases"] = phase_breakdown(rbd, X32, args.d_max, weights=w64)
+        del rw["bufs"], rw["res"]
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:

@@ -59,3 +59,53 @@ def test_parametric_field_full_size(dtype):
     cols = [0, 1, 2, 255, 256, 509, 510, 511]
     G = Y[:, cols].T @ Y[:, cols]
     assert np.max(np.abs(G - np.eye(len(cols)))) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_parametric_field_full_size_weighted(dtype):
+    """Diagonal A (a disc of grid points weighted 100x) at full size.
+
+    Sampled checks: T = Y'X and the A-norm errors of sampled columns; the
+    pivot taken at step k had A-norm error E_k against the first k vectors.
+    """
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    print(f"[gpu] weighted parametric field 1048576 x 4096 dtype={dtype} d_max=512", flush=True)
+    pf = synth.parametric_field(seed=0)
+    w = synth.disc_weights(1024)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    X = torch.empty((pf.m, pf.n), dtype=tdt, device="cuda:0")
+    pf.fill_device(X)
+    res = rbd.fit(X, tol=0.0, d_max=512, weights=torch.from_numpy(w).to("cuda:0"))
+    del X
+    torch.cuda.empty_cache()
+    assert res.d == 512 and res.stop == "dmax"
+    piv = res.pivots.cpu().numpy()
+    hist = res.err_hist.cpu().numpy()
+    col_err = res.col_err.cpu().numpy()
+    T = res.T.cpu().numpy()
+    Y = res.Y.cpu().numpy()
+    E0 = hist[0]
+    assert len(set(piv.tolist())) == 512
+    B = T[:, piv]
+    assert np.all(np.diag(B) > 0) and np.max(np.abs(np.tril(B, -1))) <= 1e-9 * np.abs(B).max()
+    assert abs(hist[-1] - col_err.max()) <= 1e-12 * E0
+    g = np.random.default_rng(8)
+    steps = [0, 1, 2, 100, 511]
+    J = np.unique(np.concatenate([g.choice(pf.n, 5, replace=False), piv[steps]]))
+    Xj = synth.quantize(pf.columns(J), dtype)[1]
+    nx = np.linalg.norm(Xj, axis=0)
+    assert np.max(np.abs(Y.T @ Xj - T[:, J]) / nx) <= 1e-12
+
+    def anorm(R):
+        return np.sqrt(w @ (R * R))
+
+    true_err = anorm(Xj - Y @ T[:, J])
+    true_err[np.isin(J, piv)] = 0.0
+    assert np.max(np.abs(true_err - col_err[J])) <= 1e-5 * E0
+    for k in steps:
+        jj = int(np.searchsorted(J, piv[k]))
+        x = Xj[:, jj]
+        e_k = anorm((x - Y[:, :k] @ T[:k, piv[k]])[:, None])[0]
+        assert abs(e_k - hist[k]) <= 1e-5 * E0, (k, e_k, hist[k])
