@@ -120,16 +120,18 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_bres_i = take(8 * P->up_ncb);
     P->o_v1 = take(8 * m);
     P->o_v2 = take(8 * m);
-    P->o_h2 = take(8 * (size_t)RBD_MAX_D);
+    P->o_h2 = take(8 * 2 * ((size_t)RBD_MAX_D + 1));   // two h2 buffers (lagged path: this step and the last)
     P->o_nu2 = take(8);
     P->o_g = take(8 * m);
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
     // scan partials (two rows of n per slab with a diagonal A-norm); Gram-Schmidt partials
-    const size_t part_elems = std::max<size_t>((size_t)P->sc_S * 2 * n,
+    // (the lagged path adds up to ceil(D / kTcorr) correction rows after the scan's slabs)
+    const size_t kp_max = (size_t)cdiv(std::max(P->D, 1), kTcorr);
+    const size_t part_elems = std::max<size_t>(std::max<size_t>((size_t)P->sc_S * 2 * n, ((size_t)P->sc_S + kp_max) * n),
                                                (size_t)P->cg_S * (std::max(P->D, 1) + 2));
     P->o_part = take(8 * part_elems);
     const size_t l2_elems =
-        std::max<size_t>((size_t)P->up_SG * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
+        std::max<size_t>(((size_t)P->up_SG + kp_max + 1) * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
     P->o_l2 = take(8 * l2_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * n);
     P->total = o;
@@ -237,6 +239,33 @@ void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, co
                                                                     P.cg_rows, v1, part, std::max(P.D, 1));
 }
 
+template <typename Tx, int KC>
+void launch_cgs1_lag(const FitPlan& P, const Tx* X, int64_t ldx, double* Y, const double* T, State* st, int d,
+                     const double* v1p, const double* h2p, double* v1, double* part, hipStream_t s) {
+    cgs1_lag_kernel<Tx, KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                        P.cg_rows, v1p, h2p, v1, part,
+                                                                        std::max(P.D, 1));
+}
+
+template <int KC, bool FINAL>
+void launch_ycol(const FitPlan& P, double* Y, const State* st, int d, const double* v1a, const double* v1b,
+                 const double* h2a, const double* h2b, hipStream_t s) {
+    ycol_kernel<KC, rows_in_flight(KC), FINAL><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1a, v1b,
+                                                                       h2a, h2b);
+}
+
+template <bool FINAL>
+void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d, const double* v1a,
+                    const double* v1b, const double* h2a, const double* h2b, hipStream_t s) {
+    switch (kc) {
+        case 1: launch_ycol<1, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+        case 2: launch_ycol<2, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+        case 4: launch_ycol<4, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+        case 8: launch_ycol<8, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+        default: launch_ycol<16, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+    }
+}
+
 template <int KC>
 void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
                  double* v2, double* part, const double* w, hipStream_t s) {
@@ -314,7 +343,66 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_INIT, s);
 
-    for (int d = 0; d < P.D; ++d) {
+    // A = I: lagged reorthogonalisation, one pass over Y per step.  v1 and h2
+    // alternate between two buffers by the parity of the step.
+    double* const v1s[2] = {v1, v2};
+    double* const h2s[2] = {h2, h2 + RBD_MAX_D + 1};
+    for (int d = 0; !W && d < P.D; ++d) {
+        const int c = d & 1;
+        const int kc = kc_for(d);
+        prof_begin(RBD_PHASE_CGS1, s);
+        switch (kc) {
+            case 1: launch_cgs1_lag<Tx, 1>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 2: launch_cgs1_lag<Tx, 2>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 4: launch_cgs1_lag<Tx, 4>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 8: launch_cgs1_lag<Tx, 8>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            default: launch_cgs1_lag<Tx, 16>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_CGS1, s);
+        prof_begin(RBD_PHASE_CGS2, s);
+        nu_lag_kernel<<<1, 256, 0, s>>>(st, h2s[c], d);
+        RBD_LAUNCH_CHECK();
+        const int kp = d > 0 ? (int)cdiv(d, kTcorr) : 0;
+        if (kp) {
+            tcorr_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)kp), 256, 0, s>>>(
+                st, h2s[c], d, T, P.n, P.n, part + (int64_t)P.sc_S * P.n);
+            RBD_LAUNCH_CHECK();
+        }
+        prof_end(RBD_PHASE_CGS2, s);
+        prof_begin(RBD_PHASE_XSCAN, s);
+        launch_xscan<Tx, kScanDot>(P, X, ldx, v1s[c], st, Y, -1, part, vec_ok, nt, s);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_XSCAN, s);
+        prof_begin(RBD_PHASE_UPDATE, s);
+        const int rows = P.sc_S + kp;
+        const int groups = (int)cdiv(rows, up_per);
+        reduce_rows_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)groups), 256, 0, s>>>(st, part, P.n, rows,
+                                                                                           up_per, P.n, l2, P.n);
+        RBD_LAUNCH_CHECK();
+        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n, flags,
+                                                      flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_UPDATE, s);
+        prof_begin(RBD_PHASE_RESID, s);
+        // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
+        launch_ycol_kc<false>(kc, P, Y, st, d, v1s[0], v1s[1], h2s[0], h2s[1], s);
+        RBD_LAUNCH_CHECK();
+        resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+                                                    P.rc_rows, P.rc_S, rpart, P.n, nullptr);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_RESID, s);
+        prof_begin(RBD_PHASE_RESID_FINISH, s);
+        resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, rpart, P.n, P.rc_S, flist, e2, base2, P.n, tickets, pivots,
+                                                      err_hist, d);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_RESID_FINISH, s);
+        prof_step(s);
+    }
+    // diagonal A: explicit second pass (it also forms the A-weighted sums)
+    for (int d = 0; W && d < P.D; ++d) {
         prof_begin(RBD_PHASE_CGS1, s);
         switch (kc_for(d)) {
             case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, s); break;
@@ -388,6 +476,11 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
     const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
     prof_begin(RBD_PHASE_EPILOGUE, s);
+    if (!W) {
+        // the last basis vector is still implicit: write it
+        launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], s);
+        RBD_LAUNCH_CHECK();
+    }
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
                                        stop_reason);
     RBD_LAUNCH_CHECK();

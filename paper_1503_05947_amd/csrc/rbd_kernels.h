@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
             const double xi = v2[r0 + r] * inv;
             xi_s[r] = xi;
             if (TWO) xi_s[rows_per_slab + r] = g2[r0 + r];
-            if (DOT && tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
+            if (DOT && dcol >= 0 && tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
         }
         __syncthreads();
     }
@@ -492,6 +492,199 @@ __global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y,
 #pragma unroll
         for (int u = 0; u < RU; ++u)
             if (lane == u && rb + u < r1) g[rb + u] = (w[rb + u] * v2[rb + u] - dot[u]) * inv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lagged reorthogonalisation (A = I).  The second Gram-Schmidt pass of step d
+// is not formed as a vector: with v1 the first-pass vector and
+// h2 = Y(:, 0:d)' v1, the new basis vector is xi = (v1 - Y h2) / nu, where
+// nu^2 = ||v1||^2 - ||h2||^2 (v1 - Y h2 is orthogonal to Y), and its row of T is
+//   T(d, :) = xi' X = (v1' X - h2' T(0:d, :)) / nu        (T(0:d, :) = Y' X).
+// The column xi itself is written by the next step's first pass, which reads
+// Y anyway; so each step reads Y once instead of twice.
+// ---------------------------------------------------------------------------
+
+// cgs1_lag: first forms this row's entry of the deferred column d-1,
+//   Y(i, d-1) = (v1p_i - Y(i, 0:d-1) h2p) / nu_prev,
+// stores it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
+// share of h2 = Y(:, 0:d)' v1 (part[blk*ldp + k], k < d) and of ||v1||^2
+// (part[blk*ldp + d]).
+template <typename Tx, int KC, int RU>
+__global__ __launch_bounds__(256) void cgs1_lag_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                        double* __restrict__ Y, int64_t ldy,
+                                                        const double* __restrict__ T, int64_t ldt,
+                                                        State* __restrict__ st, int d, int rows_per_blk,
+                                                        const double* __restrict__ v1p,
+                                                        const double* __restrict__ h2p, double* __restrict__ v1,
+                                                        double* __restrict__ part, int64_t ldp) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    __shared__ double gs[KW];
+    __shared__ double accs[KW];
+    __shared__ double sred[4];
+    const int p = st->p;
+    const double invp = st->inv_nu;               // 1/nu of the previous step
+    const int dl = d - 1;                          // the deferred column (none at d = 0)
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? T[(int64_t)k * ldt + p] : 0.0;
+        gs[k] = (k < dl) ? h2p[k] : 0.0;
+        accs[k] = 0.0;
+    }
+    __syncthreads();
+    const double hl = dl >= 0 ? hs[dl] : 0.0;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int cl = dl >= 0 ? dl / kWave : -1, ll = dl >= 0 ? dl % kWave : -1;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    double nacc = 0.0;
+    for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+        double xv[RU], vp[RU];
+        double dots[2 * RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+            xv[u] = ok ? Ld<Tx>::one(X + r * ldx + p) : 0.0;
+            vp[u] = (ok && dl >= 0) ? v1p[r] : 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < dl) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                a = fma(y[u][c], gs[lane + kWave * c], a);
+                b = fma(y[u][c], hs[lane + kWave * c], b);
+            }
+            dots[u] = a;
+            dots[RU + u] = b;
+        }
+        wave_sum_n<2 * RU>(dots);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const double yl = dl >= 0 ? (vp[u] - dots[u]) * invp : 0.0;   // rows past the end give 0
+            const double v = xv[u] - dots[RU + u] - yl * hl;
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+                if (c == cl && lane == ll) y[u][c] = yl;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
+            if (lane == u && r < r1) {
+                v1[r] = v;
+                nacc = fma(v, v, nacc);
+                if (dl >= 0) Y[r * ldy + dl] = yl;
+            }
+        }
+    }
+    const double nn = block_sum(nacc, sred);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (w == q) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += acc[c];
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
+}
+
+// nu_lag: h2[0:d] and h2[d] = ||v1||^2 summed; nu^2 = ||v1||^2 - ||h2||^2 and
+// step 2.2's break test.
+__global__ __launch_bounds__(256) void nu_lag_kernel(State* __restrict__ st, const double* __restrict__ h2, int d) {
+    if (st->stop) return;
+    __shared__ double sred[4];
+    double q = 0.0;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) q = fma(h2[k], h2[k], q);
+    q = block_sum(q, sred);
+    if (threadIdx.x == 0) {
+        const double s = h2[d] - q;
+        const double nu = s > 0.0 ? sqrt(s) : 0.0;
+        st->nu = nu;
+        if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
+        else st->inv_nu = 1.0 / nu;
+    }
+}
+
+// tcorr: the correction rows -h2' T(0:d, :) / nu, one partial row per chunk of
+// kTcorr rows of T (grid: column blocks x chunks); summed after the scan's
+// slab partials in a fixed order.
+constexpr int kTcorr = 32;
+__global__ __launch_bounds__(256) void tcorr_kernel(const State* __restrict__ st, const double* __restrict__ h2,
+                                                     int d, const double* __restrict__ T, int64_t ldt, int64_t n,
+                                                     double* __restrict__ out) {
+    if (st->stop) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int k0 = blockIdx.y * kTcorr, k1 = min(d, k0 + kTcorr);
+    double c = 0.0;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) c = fma(h2[k], T[(int64_t)k * ldt + j], c);
+    out[(int64_t)blockIdx.y * n + j] = -c * st->inv_nu;
+}
+
+// ycol: writes the deferred column, Y(:, col) = (v1 - Y(:, 0:col) h2) / nu.
+// FINAL = false: col = d, before an exact refresh of this step (skipped when
+// none is queued).  FINAL = true: col = (final d) - 1, after the loop; the
+// buffers of that step are chosen by the parity of col.
+template <int KC, int RU, bool FINAL>
+__global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                    const State* __restrict__ st, int d, int rows_per_blk,
+                                                    const double* __restrict__ v1a, const double* __restrict__ v1b,
+                                                    const double* __restrict__ h2a, const double* __restrict__ h2b) {
+    int col;
+    if (FINAL) {
+        if (st->stop == kStopError) return;
+        col = st->d - 1;
+        if (col < 0) return;
+    } else {
+        if (st->stop || st->nflag == 0) return;
+        col = d;
+    }
+    const double* v1 = (col & 1) ? v1b : v1a;
+    const double* h2 = (col & 1) ? h2b : h2a;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < col) ? h2[k] : 0.0;
+    __syncthreads();
+    const double inv = st->inv_nu;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < col) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+        double dot[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            dot[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
+        }
+        wave_sum_n<RU>(dot);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (lane == u && rb + u < r1) Y[(rb + u) * ldy + col] = (v1[rb + u] - dot[u]) * inv;
     }
 }
 
