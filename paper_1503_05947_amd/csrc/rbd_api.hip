@@ -50,7 +50,7 @@ struct FitPlan {
     int ntickets = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
-    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_hw,
+    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_hw,
         o_part,
         o_l2, o_rpart, total;
 };
@@ -123,6 +123,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_h2 = take(8 * 2 * ((size_t)RBD_MAX_D + 1));   // two h2 buffers (lagged path: this step and the last)
     P->o_nu2 = take(8);
     P->o_g = take(8 * m);
+    P->o_xp = take(8 * m);
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
     // scan partials (two rows of n per slab with a diagonal A-norm); Gram-Schmidt partials
     // (the lagged path adds up to ceil(D / kTcorr) correction rows after the scan's slabs)
@@ -232,19 +233,24 @@ void launch_xscan(const FitPlan& P, const Tx* X, int64_t ldx, const double* v2, 
 // more of them in flight; long rows are limited by registers.
 constexpr int rows_in_flight(int KC) { return KC <= 2 ? 8 : (KC <= 8 ? 4 : 2); }
 
-template <typename Tx, int KC>
-void launch_cgs1(const FitPlan& P, const Tx* X, int64_t ldx, const double* Y, const double* T, State* st,
-                 int d, double* v1, double* part, hipStream_t s) {
-    cgs1_kernel<Tx, KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                    P.cg_rows, v1, part, std::max(P.D, 1));
+template <int KC>
+void launch_cgs1(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
+                 double* v1, double* part, hipStream_t s) {
+    cgs1_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, v1,
+                                                                part, std::max(P.D, 1));
 }
 
-template <typename Tx, int KC>
-void launch_cgs1_lag(const FitPlan& P, const Tx* X, int64_t ldx, double* Y, const double* T, State* st, int d,
+template <int KC>
+void launch_cgs1_lag(const FitPlan& P, const double* xp, double* Y, const double* T, State* st, int d,
                      const double* v1p, const double* h2p, double* v1, double* part, hipStream_t s) {
-    cgs1_lag_kernel<Tx, KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                        P.cg_rows, v1p, h2p, v1, part,
-                                                                        std::max(P.D, 1));
+    cgs1_lag_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows,
+                                                                    v1p, h2p, v1, part, std::max(P.D, 1));
+}
+
+template <typename Tx>
+void launch_gather(const FitPlan& P, const Tx* X, int64_t ldx, const State* st, double* xp, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(16384, cdiv(P.m, 256));
+    gather_col_kernel<Tx><<<g, 256, 0, s>>>(X, ldx, P.m, st, xp);
 }
 
 template <int KC, bool FINAL>
@@ -313,6 +319,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
     double* g = reinterpret_cast<double*>(ws + P.o_g);
     double* hw = reinterpret_cast<double*>(ws + P.o_hw);
+    double* xp = reinterpret_cast<double*>(ws + P.o_xp);
     const bool W = (w != nullptr);
     const int64_t nw = W ? 2 * P.n : P.n;     // scan partial row length
 
@@ -351,12 +358,14 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         const int c = d & 1;
         const int kc = kc_for(d);
         prof_begin(RBD_PHASE_CGS1, s);
+        launch_gather<Tx>(P, X, ldx, st, xp, s);
+        RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs1_lag<Tx, 1>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 2: launch_cgs1_lag<Tx, 2>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 4: launch_cgs1_lag<Tx, 4>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 8: launch_cgs1_lag<Tx, 8>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            default: launch_cgs1_lag<Tx, 16>(P, X, ldx, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 1: launch_cgs1_lag<1>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 2: launch_cgs1_lag<2>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 4: launch_cgs1_lag<4>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 8: launch_cgs1_lag<8>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            default: launch_cgs1_lag<16>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
@@ -390,7 +399,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
         launch_ycol_kc<false>(kc, P, Y, st, d, v1s[0], v1s[1], h2s[0], h2s[1], s);
         RBD_LAUNCH_CHECK();
-        resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+        resid_mfma_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, nullptr);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID, s);
@@ -404,12 +413,14 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     // diagonal A: explicit second pass (it also forms the A-weighted sums)
     for (int d = 0; W && d < P.D; ++d) {
         prof_begin(RBD_PHASE_CGS1, s);
+        launch_gather<Tx>(P, X, ldx, st, xp, s);
+        RBD_LAUNCH_CHECK();
         switch (kc_for(d)) {
-            case 1: launch_cgs1<Tx, 1>(P, X, ldx, Y, T, st, d, v1, part, s); break;
-            case 2: launch_cgs1<Tx, 2>(P, X, ldx, Y, T, st, d, v1, part, s); break;
-            case 4: launch_cgs1<Tx, 4>(P, X, ldx, Y, T, st, d, v1, part, s); break;
-            case 8: launch_cgs1<Tx, 8>(P, X, ldx, Y, T, st, d, v1, part, s); break;
-            default: launch_cgs1<Tx, 16>(P, X, ldx, Y, T, st, d, v1, part, s); break;
+            case 1: launch_cgs1<1>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 2: launch_cgs1<2>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 4: launch_cgs1<4>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 8: launch_cgs1<8>(P, xp, Y, T, st, d, v1, part, s); break;
+            default: launch_cgs1<16>(P, xp, Y, T, st, d, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         if (d > 0) {
@@ -462,7 +473,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
-        resid_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+        resid_mfma_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, w);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID, s);
@@ -528,7 +539,7 @@ int project_typed(const ProjPlan& P, const double* Y, int64_t ldy, int64_t m, in
     const int64_t len = (int64_t)d * k;
     sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(len, 256)), 256, 0, s>>>(part, P.S, len, Tv_out, 0);
     RBD_LAUNCH_CHECK();
-    resid_kernel<Tv><<<P.rc_grid, 256, 0, s>>>(V, ldv, m, Y, ldy, d, Tv_out, k, nullptr, nullptr, (int)k, P.rc_rows,
+    resid_mfma_kernel<Tv><<<P.rc_grid, 256, 0, s>>>(V, ldv, m, Y, ldy, d, Tv_out, k, nullptr, nullptr, (int)k, P.rc_rows,
                                                P.rc_S, rpart, k, nullptr);
     RBD_LAUNCH_CHECK();
     sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(k, 256)), 256, 0, s>>>(rpart, P.rc_S, k, err_v, 1);

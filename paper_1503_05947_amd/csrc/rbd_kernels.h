@@ -297,12 +297,33 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
 }
 
 // ---------------------------------------------------------------------------
+// gather_col: xp = X(:, p) widened to FP64 into a contiguous vector.  One row
+// per thread, so the whole strided column is in flight at once.
+// ---------------------------------------------------------------------------
+template <typename Tx>
+__global__ __launch_bounds__(256) void gather_col_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                          const State* __restrict__ st, double* __restrict__ xp) {
+    if (st->stop) return;
+    const int64_t p = st->p;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += stride)
+        xp[r] = Ld<Tx>::one(X + r * ldx + p);
+}
+
+// value of lane u (wave-uniform u) in every lane
+__device__ __forceinline__ double lane_bcast(double v, int u) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), u);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), u);
+    return __hiloint2double(hi, lo);
+}
+
+// ---------------------------------------------------------------------------
 // cgs1: v1 = x_p - Y(:, 0:d) h1, h1 = T(0:d, p); partial h2 = Y' v1 per block.
 // One wave per row of Y (lanes run along k), RU rows in flight per wave; the
 // wave keeps its share of h2 in registers, so Y is read once.
 // ---------------------------------------------------------------------------
-template <typename Tx, int KC, int RU>
-__global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp, int64_t m,
                                                     const double* __restrict__ Y, int64_t ldy,
                                                     const double* __restrict__ T, int64_t ldt,
                                                     State* __restrict__ st, int d, int rows_per_blk,
@@ -332,7 +353,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const Tx* __restrict__ X, int
         for (int u = 0; u < RU; ++u) {
             const int64_t r = rb + u;
             const bool ok = r < r1;
-            xv[u] = ok ? Ld<Tx>::one(X + r * ldx + p) : 0.0;
+            xv[u] = ok ? xp[r] : 0.0;
             dot[u] = 0.0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
@@ -510,14 +531,15 @@ __global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y,
 // stores it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
 // share of h2 = Y(:, 0:d)' v1 (part[blk*ldp + k], k < d) and of ||v1||^2
 // (part[blk*ldp + d]).
-template <typename Tx, int KC, int RU>
-__global__ __launch_bounds__(256) void cgs1_lag_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict__ xp, int64_t m,
                                                         double* __restrict__ Y, int64_t ldy,
                                                         const double* __restrict__ T, int64_t ldt,
                                                         State* __restrict__ st, int d, int rows_per_blk,
                                                         const double* __restrict__ v1p,
                                                         const double* __restrict__ h2p, double* __restrict__ v1,
                                                         double* __restrict__ part, int64_t ldp) {
+    static_assert(RU <= kWave, "one lane per row in flight");
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -543,15 +565,17 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const Tx* __restrict__ X,
     for (int c = 0; c < KC; ++c) acc[c] = 0.0;
     double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+        // lane u < RU carries row rb + u's scalars (one load / store instruction per group)
+        const int64_t rl = rb + lane;
+        const bool okl = lane < RU && rl < r1;
+        const double xl = okl ? xp[rl] : 0.0;
+        const double vl = (okl && dl >= 0) ? v1p[rl] : 0.0;
         double y[RU][KC];
-        double xv[RU], vp[RU];
         double dots[2 * RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t r = rb + u;
             const bool ok = r < r1;
-            xv[u] = ok ? Ld<Tx>::one(X + r * ldx + p) : 0.0;
-            vp[u] = (ok && dl >= 0) ? v1p[r] : 0.0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
@@ -570,21 +594,22 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const Tx* __restrict__ X,
             dots[RU + u] = b;
         }
         wave_sum_n<2 * RU>(dots);
+        double vo = 0.0, yo = 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const int64_t r = rb + u;
-            const double yl = dl >= 0 ? (vp[u] - dots[u]) * invp : 0.0;   // rows past the end give 0
-            const double v = xv[u] - dots[RU + u] - yl * hl;
+            const double yl = dl >= 0 ? (lane_bcast(vl, u) - dots[u]) * invp : 0.0;   // rows past the end: 0
+            const double v = lane_bcast(xl, u) - dots[RU + u] - yl * hl;
 #pragma unroll
             for (int c = 0; c < KC; ++c)
                 if (c == cl && lane == ll) y[u][c] = yl;
 #pragma unroll
             for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
-            if (lane == u && r < r1) {
-                v1[r] = v;
-                nacc = fma(v, v, nacc);
-                if (dl >= 0) Y[r * ldy + dl] = yl;
-            }
+            if (lane == u) { vo = v; yo = yl; }
+        }
+        if (okl) {
+            v1[rl] = vo;
+            nacc = fma(vo, vo, nacc);
+            if (dl >= 0) Y[rl * ldy + dl] = yo;
         }
     }
     const double nn = block_sum(nacc, sred);
@@ -735,29 +760,39 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const State* __restric
 }
 
 // ---------------------------------------------------------------------------
-// resid: partial squared residual norms of listed columns,
-//   part[s * ldp + jj] = sum_{i in slab s} (X[i, c] - sum_{k<K} Y[i, k] C[k, c])^2,
-// c = J ? J[jj] : jj, for jj < count (count = *count_dev when given, else
-// count_host).  An FP64 GEMM with 128 x 128 output tiles (8 x 8 per thread,
-// operands staged in LDS 16 deep in k), the subtraction from X and the column
-// sums of squares fused.  Work items (column tile, slab) are strided over a
-// fixed grid; each writes its own partial, so the result is deterministic.
+// resid_mfma: partial squared residual norms of listed columns,
+//   part[s * ldp + jj] = sum_{i in slab s} w_i (X[i, c] - sum_{k<K} Y[i, k] C[k, c])^2,
+// c = J ? J[jj] : jj, w_i = 1 without weights, for jj < count (count =
+// *count_dev when given, else count_host).  Work items (column tile, slab)
+// are strided over a fixed grid, each writing its own partial.  The product
+// Y(:, 0:K) C(0:K, cols) runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16), accumulator register r of lane l holds C(4r + l / 16,
+// l % 16)).  Workgroup tile 128 rows x 64 columns, four waves of 32 x 64;
+// k staged through LDS 16 deep, the next chunk's global loads in flight
+// while the current chunk is multiplied.  Partial sums are combined in a
+// fixed order (lanes, then waves), so results are deterministic.
 // ---------------------------------------------------------------------------
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 template <typename Tx>
-__global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
-                                                     const double* __restrict__ Y, int64_t ldy, int K,
-                                                     const double* __restrict__ C, int64_t ldc,
-                                                     const int* __restrict__ J, const int* __restrict__ count_dev,
-                                                     int count_host, int rows_per_slab, int nslab,
-                                                     double* __restrict__ part, int64_t ldp,
-                                                     const double* __restrict__ w) {
+__global__ __launch_bounds__(256, 2) void resid_mfma_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+                                                          const double* __restrict__ Y, int64_t ldy, int K,
+                                                          const double* __restrict__ C, int64_t ldc,
+                                                          const int* __restrict__ J,
+                                                          const int* __restrict__ count_dev, int count_host,
+                                                          int rows_per_slab, int nslab, double* __restrict__ part,
+                                                          int64_t ldp, const double* __restrict__ w) {
     const int cnt = count_dev ? *count_dev : count_host;
     if (cnt == 0) return;
     constexpr int TM = 128, TN = 64, KB = 16;
+    constexpr int YQ = TM * KB / 256, CQ = KB * TN / 256;
     __shared__ double Ys[TM][KB + 1];
     __shared__ double Cs[KB][TN + 1];
+    __shared__ double red[4][TN];
     __shared__ int cols[TN];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int lr = lane % 16, lk = lane / 16;
     const int ntiles = (cnt + TN - 1) / TN;
     const int nwork = ntiles * nslab;
     for (int wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
@@ -770,69 +805,88 @@ __global__ __launch_bounds__(256) void resid_kernel(const Tx* __restrict__ X, in
         __syncthreads();
         const int64_t rbeg = (int64_t)s * rows_per_slab;
         const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
-        double rs[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) rs[b] = 0.0;
+        double rs[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t row0 = rbeg; row0 < rend; row0 += TM) {
-            double acc[8][4];
+            f64x4_t acc[2][4];
 #pragma unroll
-            for (int a = 0; a < 8; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-            for (int k0 = 0; k0 < K; k0 += KB) {
+                for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+            double yr[YQ], cr[CQ];
+            auto load = [&](int k0) {
 #pragma unroll
-                for (int q = 0; q < (TM * KB) / 256; ++q) {
+                for (int q = 0; q < YQ; ++q) {
                     const int e = tid + 256 * q;
                     const int rr = e / KB, kk = e % KB;
                     const int64_t row = row0 + rr;
                     const int k = k0 + kk;
-                    Ys[rr][kk] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
+                    yr[q] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
                 }
 #pragma unroll
-                for (int q = 0; q < (TN * KB) / 256; ++q) {
+                for (int q = 0; q < CQ; ++q) {
                     const int e = tid + 256 * q;
                     const int kk = e / TN, cc = e % TN;
                     const int k = k0 + kk;
                     const int col = cols[cc];
-                    Cs[kk][cc] = (k < K && col >= 0) ? C[(int64_t)k * ldc + col] : 0.0;
+                    cr[q] = (k < K && col >= 0) ? C[(int64_t)k * ldc + col] : 0.0;
                 }
+            };
+            load(0);
+            for (int k0 = 0; k0 < K; k0 += KB) {
                 __syncthreads();
 #pragma unroll
-                for (int kk = 0; kk < KB; ++kk) {
-                    double yv[8], cv[4];
+                for (int q = 0; q < YQ; ++q) {
+                    const int e = tid + 256 * q;
+                    Ys[e / KB][e % KB] = yr[q];
+                }
 #pragma unroll
-                    for (int a = 0; a < 8; ++a) yv[a] = Ys[ty + 16 * a][kk];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) cv[b] = Cs[kk][tx + 16 * b];
-#pragma unroll
-                    for (int a = 0; a < 8; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], cv[b], acc[a][b]);
+                for (int q = 0; q < CQ; ++q) {
+                    const int e = tid + 256 * q;
+                    Cs[e / TN][e % TN] = cr[q];
                 }
                 __syncthreads();
+                if (k0 + KB < K) load(k0 + KB);
+#pragma unroll
+                for (int ks = 0; ks < KB; ks += 4) {
+                    double af[2], bf[4];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) af[a] = Ys[32 * wv + 16 * a + lr][ks + lk];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) bf[b] = Cs[ks + lk][16 * b + lr];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+                }
             }
+            // r = X - Y C, squared and summed per column
 #pragma unroll
-            for (int a = 0; a < 8; ++a) {
-                const int64_t row = row0 + ty + 16 * a;
+            for (int b = 0; b < 4; ++b) {
+                const int col = cols[16 * b + lr];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int col = cols[tx + 16 * b];
-                    if (row < rend && col >= 0) {
-                        const double r = Ld<Tx>::one(X + row * ldx + col) - acc[a][b];
-                        rs[b] = w ? fma(w[row] * r, r, rs[b]) : fma(r, r, rs[b]);
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
+                        if (row < rend && col >= 0) {
+                            const double d = Ld<Tx>::one(X + row * ldx + col) - acc[a][b][r];
+                            rs[b] = w ? fma(w[row] * d, d, rs[b]) : fma(d, d, rs[b]);
+                        }
                     }
-                }
             }
         }
-        // column sums over the 16 row groups, in order
-        __syncthreads();
-        double* red = &Ys[0][0];   // reuse: 16 x 64 doubles fit in Ys (128 x 17)
+        // column cc = 16 b + lane % 16: sum the four lane groups, then the four waves
 #pragma unroll
-        for (int b = 0; b < 4; ++b) red[ty * TN + tx + 16 * b] = rs[b];
+        for (int b = 0; b < 4; ++b) {
+            double v = rs[b];
+            v += __shfl_xor(v, 16, kWave);
+            v += __shfl_xor(v, 32, kWave);
+            if (lk == 0) red[wv][16 * b + lr] = v;
+        }
         __syncthreads();
         if (tid < TN) {
-            double sum = 0.0;
-            for (int q = 0; q < 16; ++q) sum += red[q * TN + tid];
+            const double sum = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
             const int jj = t * TN + tid;
             if (jj < cnt) part[(int64_t)s * ldp + jj] = sum;
         }
