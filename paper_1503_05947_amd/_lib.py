@@ -74,6 +74,12 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} not found: build it with __graft_entry__.build() "
                              "(there is no fallback implementation)")
+    # torch brings its own HIP runtime; it must be the one librbd binds to, or
+    # torch's streams and memory are foreign to the library's launches
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

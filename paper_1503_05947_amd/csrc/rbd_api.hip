@@ -50,7 +50,7 @@ struct FitPlan {
     int ntickets = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
-    size_t o_state, o_tickets, o_e2, o_base2, o_flags, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_hw,
+    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_hw,
         o_part,
         o_l2, o_rpart, total;
 };
@@ -114,7 +114,6 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_tickets = take(sizeof(unsigned) * P->ntickets);
     P->o_e2 = take(8 * n);
     P->o_base2 = take(8 * n);
-    P->o_flags = take(4 * n);
     P->o_flist = take(4 * n);
     P->o_bres_v = take(8 * P->up_ncb);
     P->o_bres_i = take(8 * P->up_ncb);
@@ -307,7 +306,6 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     unsigned* tickets = reinterpret_cast<unsigned*>(ws + P.o_tickets);
     double* e2 = reinterpret_cast<double*>(ws + P.o_e2);
     double* base2 = reinterpret_cast<double*>(ws + P.o_base2);
-    int* flags = reinterpret_cast<int*>(ws + P.o_flags);
     int* flist = reinterpret_cast<int*>(ws + P.o_flist);
     double* bres_v = reinterpret_cast<double*>(ws + P.o_bres_v);
     int64_t* bres_i = reinterpret_cast<int64_t*>(ws + P.o_bres_i);
@@ -328,9 +326,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const bool nt = (double)P.m * (double)ldx * sizeof(Tx) > 512.0 * 1024 * 1024;
 
     prof_fit_begin(s);
-    const int64_t nflags = P.n;
-    init_state_kernel<<<(unsigned)std::min<int64_t>(1024, cdiv(std::max<int64_t>(nflags, P.ntickets), 256)), 256, 0,
-                        s>>>(st, tickets, P.ntickets, P.D, flags, nflags);
+    init_state_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(P.ntickets, 256))), 256, 0, s>>>(st, tickets,
+                                                                                              P.ntickets, P.D);
     RBD_LAUNCH_CHECK();
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
     prof_begin(RBD_PHASE_COLNORM, s);
@@ -345,7 +342,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const int up_groups = (int)cdiv(P.sc_S, up_per);
     reduce_rows_kernel<<<red_grid, 256, 0, s>>>(nullptr, part, P.n, P.sc_S, up_per, P.n, l2, P.n);
     RBD_LAUNCH_CHECK();
-    update_kernel<kInit><<<P.up_ncb, 256, 0, s>>>(P.n, st, 0, l2, up_groups, tickets, e2, base2, T, P.n, flags, flist,
+    update_kernel<kInit><<<P.up_ncb, 256, 0, s>>>(P.n, st, 0, l2, up_groups, tickets, e2, base2, T, P.n, flist,
                                                   bres_v, bres_i, pivots, err_hist, start, tol, rel);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_INIT, s);
@@ -391,7 +388,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         reduce_rows_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)groups), 256, 0, s>>>(st, part, P.n, rows,
                                                                                            up_per, P.n, l2, P.n);
         RBD_LAUNCH_CHECK();
-        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n, flags,
+        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n,
                                                       flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
@@ -465,10 +462,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         reduce_rows_kernel<<<red_grid_step, 256, 0, s>>>(st, part, nw, P.sc_S, up_per, nw, l2, nw);
         RBD_LAUNCH_CHECK();
         if (W)
-            update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
+            update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n,
                                                            flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         else
-            update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flags,
+            update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n,
                                                           flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);

@@ -17,6 +17,7 @@ namespace rbd {
 constexpr int kWave = 64;
 constexpr int kStopError = 4;           // internal stop code: non-finite input
 constexpr double kRefresh = 0x1p-20;    // kappa: re-evaluate a column exactly when e^2 < kappa * (last exact e^2)
+constexpr double kRefreshEager = 0x1p-15;   // once any column needs it, also refresh those below this fraction
 
 // ---------------------------------------------------------------------------
 // loop state kept in device memory (one per rbd_fit call)
@@ -66,12 +67,14 @@ template <> struct Ld<float> {
         o[0] = r.x; o[1] = r.y; o[2] = r.z; o[3] = r.w;
     }
     static __device__ __forceinline__ double one(const float* p) { return (double)*p; }
+    static __device__ __forceinline__ double from(float v) { return (double)v; }
 };
 template <> struct Ld<double> {
     static constexpr int N = 2;
     using raw = f64x2;
     static __device__ __forceinline__ void cvt(raw r, double* o) { o[0] = r.x; o[1] = r.y; }
     static __device__ __forceinline__ double one(const double* p) { return *p; }
+    static __device__ __forceinline__ double from(double v) { return v; }
 };
 template <> struct Ld<bf16_t> {
     static constexpr int N = 8;
@@ -83,6 +86,7 @@ template <> struct Ld<bf16_t> {
     static __device__ __forceinline__ double one(const bf16_t* p) {
         return (double)__uint_as_float((unsigned)p->u << 16);
     }
+    static __device__ __forceinline__ double from(bf16_t v) { return (double)__uint_as_float((unsigned)v.u << 16); }
 };
 template <> struct Ld<f16_t> {
     static constexpr int N = 8;
@@ -94,6 +98,7 @@ template <> struct Ld<f16_t> {
     static __device__ __forceinline__ double one(const f16_t* p) {
         return (double)(float)__builtin_bit_cast(_Float16, p->u);
     }
+    static __device__ __forceinline__ double from(f16_t v) { return (double)(float)__builtin_bit_cast(_Float16, v.u); }
 };
 
 // ---------------------------------------------------------------------------

@@ -48,11 +48,10 @@ __device__ __forceinline__ void finish_step(State* st, int d, double vmax, int64
 }
 
 // ---------------------------------------------------------------------------
-__global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, int D, int* flags, int64_t nflags) {
+__global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, int D) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < ntickets; i += stride) tickets[i] = 0u;
-    for (int64_t i = gid; i < nflags; i += stride) flags[i] = 0;
     if (gid == 0) {
         st->d = 0; st->p = 0; st->stop = 0; st->status = RBD_OK; st->nflag = 0; st->D = D;
         st->nonfinite = 0; st->pad0 = 0;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
                                                       const double* __restrict__ l2, int SG,
                                                       unsigned* __restrict__ tickets,
                                                       double* __restrict__ e2, double* __restrict__ base2,
-                                                      double* __restrict__ T, int64_t ldt, int* __restrict__ flags,
+                                                      double* __restrict__ T, int64_t ldt,
                                                       int* __restrict__ flist,
                                                       double* __restrict__ bres_v, int64_t* __restrict__ bres_i,
                                                       int64_t* __restrict__ pivots, double* __restrict__ err_hist,
@@ -239,10 +238,7 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
                 base2[j] = 0.0;
             }
             e2[j] = e;
-            if (e < kRefresh * b) {
-                flags[j] = 1;
-                atomicAdd(&st->nflag, 1);
-            }
+            if (e < kRefresh * b) atomicAdd(&st->nflag, 1);
         }
         if (e == e) { best = e; bi = j; }
     }
@@ -250,13 +246,16 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
     if (threadIdx.x == 0) { bres_v[cb] = best; bres_i[cb] = bi; }
     if (!last_to_arrive(&tickets[ncb], (unsigned)ncb)) return;
     if (STEP && __hip_atomic_load(&st->nflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
-        // list the queued columns in ascending order (so neighbouring columns
-        // share the cache lines of X) and clear their flags
+        // Some column needs an exact refresh: queue every column whose
+        // downdated e^2 is below kRefreshEager of its last exact value, so
+        // the refreshes of columns that decay alike happen together (denser
+        // gathers of X, fewer refresh steps).  Ascending order, so
+        // neighbouring columns share the cache lines of X.
         __shared__ int scan[256];
         const int64_t per = (n + blockDim.x - 1) / blockDim.x;
         const int64_t a = (int64_t)threadIdx.x * per, b = min(n, a + per);
         int cnt = 0;
-        for (int64_t c = a; c < b; ++c) cnt += flags[c];
+        for (int64_t c = a; c < b; ++c) cnt += (e2[c] < kRefreshEager * base2[c]);
         scan[threadIdx.x] = cnt;
         __syncthreads();
         for (int off = 1; off < (int)blockDim.x; off <<= 1) {
@@ -267,10 +266,9 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
         }
         int pos = scan[threadIdx.x] - cnt;
         for (int64_t c = a; c < b; ++c)
-            if (flags[c]) {
-                flist[pos++] = (int)c;
-                flags[c] = 0;
-            }
+            if (e2[c] < kRefreshEager * base2[c]) flist[pos++] = (int)c;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) st->nflag = scan[threadIdx.x];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -774,9 +772,11 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const State* __restric
 // fixed order (lanes, then waves), so results are deterministic.
 // ---------------------------------------------------------------------------
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr bool kResidPrefetchX = false;    // load the tile's X entries before the products (measured: slower, spills)
+#define RBD_RESID_MIN_BLOCKS 2                // workgroups per CU the register budget is sized for
 
 template <typename Tx>
-__global__ __launch_bounds__(256, 2) void resid_mfma_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
+__global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
                                                           const double* __restrict__ Y, int64_t ldy, int K,
                                                           const double* __restrict__ C, int64_t ldc,
                                                           const int* __restrict__ J,
@@ -807,6 +807,20 @@ __global__ __launch_bounds__(256, 2) void resid_mfma_kernel(const Tx* __restrict
         const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
         double rs[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t row0 = rbeg; row0 < rend; row0 += TM) {
+            // this tile's entries of X, loaded first so that the gather's
+            // latency is covered by the products
+            Tx xr[2][4][4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int col = cols[16 * b + lr];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
+                        xr[a][b][r] = (kResidPrefetchX && row < rend && col >= 0) ? X[row * ldx + col] : Tx{};
+                    }
+            }
             f64x4_t acc[2][4];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -848,6 +862,7 @@ __global__ __launch_bounds__(256, 2) void resid_mfma_kernel(const Tx* __restrict
                 if (k0 + KB < K) load(k0 + KB);
 #pragma unroll
                 for (int ks = 0; ks < KB; ks += 4) {
+                    if (k0 + ks >= K) break;       // the last chunk's padding
                     double af[2], bf[4];
 #pragma unroll
                     for (int a = 0; a < 2; ++a) af[a] = Ys[32 * wv + 16 * a + lr][ks + lk];
@@ -870,7 +885,9 @@ __global__ __launch_bounds__(256, 2) void resid_mfma_kernel(const Tx* __restrict
                     for (int r = 0; r < 4; ++r) {
                         const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
                         if (row < rend && col >= 0) {
-                            const double d = Ld<Tx>::one(X + row * ldx + col) - acc[a][b][r];
+                            const double xv = kResidPrefetchX ? Ld<Tx>::from(xr[a][b][r])
+                                                              : Ld<Tx>::one(X + row * ldx + col);
+                            const double d = xv - acc[a][b][r];
                             rs[b] = w ? fma(w[row] * d, d, rs[b]) : fma(d, d, rs[b]);
                         }
                     }
