@@ -17,6 +17,10 @@ Contents
 ``rbd_project``  Out-of-sample compression v_C = Y' v (section 3.1, "Evaluate
                  the compression of out-of-sample data") with the A = I error
                  of eq. (3) evaluated as the norm of the explicit residual.
+``rbd_classify`` Classification of out-of-sample data in the compressed
+                 coordinates (the face recognition use of section 4): each
+                 query's coordinates c = Y' v, then the training column whose
+                 coordinates T(:, j) are nearest in the Euclidean norm.
 
 Readings where the paper is silent or ambiguous (each is listed with its
 reason in the design notes):
@@ -214,6 +218,31 @@ def rbd_project(Y, V):
     C = Y.T @ V
     err = _colnorms(V - Y @ C)
     return C, err
+
+
+def rbd_classify(Y, T, labels, V):
+    """Nearest training sample in the compressed coordinates (section 3.1's
+    out-of-sample compression used for recognition as in section 4).
+
+    c_q = Y' v_q; dist2[q, j] = sum_k (c_q[k] - T[k, j])^2 evaluated term by
+    term (no expansion into norms and a cross product); the nearest j is the
+    lowest index attaining the minimum.  Returns (index, label, dist2_min, C).
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    labels = np.asarray(labels)
+    C = Y.T @ V
+    k = C.shape[1]
+    index = np.zeros(k, dtype=np.int64)
+    best = np.zeros(k)
+    for q in range(k):
+        diff = T - C[:, q:q + 1]
+        d2 = np.sum(diff * diff, axis=0)
+        j = int(np.flatnonzero(d2 == d2.min())[0])
+        index[q] = j
+        best[q] = d2[j]
+    return index, labels[index], best, C
 
 
 def reconstruct(Y, T):

@@ -353,3 +353,88 @@ def disc_weights(grid: int, centre=(0.5, 0.5), radius: float = 0.25, hi: float =
     s = np.arange(grid, dtype=np.float64) / max(grid - 1, 1)
     inside = ((s[:, None] - centre[0]) ** 2 + (s[None, :] - centre[1]) ** 2) <= radius * radius
     return np.where(inside, float(hi), 1.0).reshape(-1)
+
+
+# ----------------------------------------------------------------------------
+# recognition workload: synthetic classes of smooth "views" on an image grid
+# (stands in for a face data set: 20 subjects, 19-48 views each, 112 x 92)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class ViewClasses:
+    """Class c's views are template_c + sum_i a_i mode_{c,i} + noise on a
+    rows x cols grid (flattened row-major).  Templates and modes are sums of
+    Gaussian bumps; a_i ~ N(0, pose), noise ~ N(0, noise)."""
+    templates: np.ndarray     # (classes, m)
+    modes: np.ndarray         # (classes, nmodes, m)
+    counts: np.ndarray        # views per class
+    pose: float
+    noise: float
+    seed: int
+
+    @property
+    def m(self) -> int:
+        return self.templates.shape[1]
+
+    def views(self, c: int, count: int, stream: int) -> np.ndarray:
+        g = rng(7, self.seed * 1009 + c, stream)
+        a = self.pose * g.standard_normal((count, self.modes.shape[1]))
+        V = self.templates[c][None, :] + a @ self.modes[c]
+        V = V + self.noise * g.standard_normal(V.shape)
+        return V.T.copy()     # (m, count)
+
+    def split(self, train_per_class: int = 10):
+        """Each class's views; the first train_per_class of a seeded shuffle
+        are training samples, the rest test samples.  Returns
+        (Xtrain, ytrain, Xtest, ytest), samples as columns."""
+        tr, ytr, te, yte = [], [], [], []
+        for c, cnt in enumerate(self.counts):
+            V = self.views(c, int(cnt), S_NOISE)
+            order = rng(7, self.seed * 1009 + c, S_SIZES).permutation(int(cnt))
+            tr.append(V[:, order[:train_per_class]])
+            te.append(V[:, order[train_per_class:]])
+            ytr += [c] * train_per_class
+            yte += [c] * (int(cnt) - train_per_class)
+        return (np.concatenate(tr, axis=1), np.array(ytr, dtype=np.int32),
+                np.concatenate(te, axis=1), np.array(yte, dtype=np.int32))
+
+    def fill_queries(self, out, labels, coeff_seed: int = 0):
+        """Device generation of many query views: out[:, q] = a view of class
+        labels[q] (torch tensors on one device; out is (m, k), any float dtype)."""
+        import torch
+        dev = out.device
+        Tm = torch.from_numpy(self.templates).to(dev)
+        Md = torch.from_numpy(self.modes).to(dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(coeff_seed))
+        k = out.shape[1]
+        step = 4096
+        for q0 in range(0, k, step):
+            lab = labels[q0:q0 + step].long()
+            a = self.pose * torch.randn((lab.numel(), Md.shape[1]), generator=gen, device=dev,
+                                        dtype=torch.float64)
+            V = Tm[lab] + torch.einsum("qi,qim->qm", a, Md[lab])
+            V += self.noise * torch.randn(V.shape, generator=gen, device=dev, dtype=torch.float64)
+            out[:, q0:q0 + lab.numel()] = V.T.to(out.dtype)
+
+
+def view_classes(seed: int = 0, classes: int = 20, rows: int = 112, cols: int = 92, lo: int = 19, hi: int = 48,
+                 nmodes: int = 3, bumps: int = 12, pose: float = 0.3, noise: float = 0.02) -> ViewClasses:
+    g = rng(7, seed, S_BUMPS)
+    s1 = np.arange(rows, dtype=np.float64) / max(rows - 1, 1)
+    s2 = np.arange(cols, dtype=np.float64) / max(cols - 1, 1)
+
+    def field():
+        F = np.zeros((rows, cols))
+        c1 = g.uniform(0.1, 0.9, bumps)
+        c2 = g.uniform(0.1, 0.9, bumps)
+        w = g.uniform(0.05, 0.25, bumps)
+        a = g.standard_normal(bumps)
+        for i in range(bumps):
+            F += a[i] * np.exp(-((s1[:, None] - c1[i]) ** 2 + (s2[None, :] - c2[i]) ** 2) / (2.0 * w[i] ** 2))
+        return F.reshape(-1)
+
+    templates = np.stack([field() for _ in range(classes)])
+    modes = np.stack([np.stack([field() for _ in range(nmodes)]) for _ in range(classes)])
+    counts = g.integers(lo, hi + 1, size=classes)
+    return ViewClasses(templates, modes, counts, pose, noise, seed)
