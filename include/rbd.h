@@ -255,6 +255,37 @@ int rbd_reconstruct_backward(const void* X, rbd_dtype xt, int64_t ldx, const voi
                              void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * rbd_classify -- recognition of out-of-sample data in the compressed
+ * coordinates: each query v (a column of V) is compressed as c = Y'v
+ * (section 3.1, "Evaluate the compression of out-of-sample data") and matched
+ * to the training sample j whose coordinates T(:, j) are nearest,
+ *   j* = argmin_j sum_i (c_i - T(i, j))^2,
+ * the differences squared and summed in FP64 term by term in ascending i; the
+ * lowest index wins ties.  This is how section 4 uses the compressed faces for
+ * recognition.
+ *   Y         m x d FP64, row-major, leading dimension ldy >= d (the basis)
+ *   T         d x n FP64, row-major, ldt >= n (training coordinates)
+ *   labels    n int32 class labels of the training samples, or NULL (the
+ *             label reported is then the index)
+ *   V         m x k queries, row-major, ldv >= k, stored as vt
+ *   C         out: d x k FP64 row-major (leading dimension k), C = Y'V
+ *   nn_index  out: k int64 nearest training index
+ *   nn_label  out: k int32 labels[nn_index]
+ *   nn_dist2  out: k FP64 squared distance to it
+ *   workspace rbd_classify_workspace_size() bytes (split-k partials of Y'V),
+ *             256-byte aligned
+ * All pointers are device memory owned by the caller; stream-ordered, no
+ * allocation or synchronisation.  Returns RBD_EINVAL for bad sizes or
+ * pointers (d > RBD_MAX_D, k >= 2^31, n < 1), RBD_EWORKSPACE when the
+ * workspace is too small, RBD_EDEVICE on a launch failure.
+ */
+int rbd_classify_workspace_size(int64_t m, int32_t d, int64_t k, size_t* bytes);
+int rbd_classify(const double* Y, int64_t ldy, int64_t m, int32_t d, const double* T, int64_t ldt, int64_t n,
+                 const int32_t* labels, const void* V, rbd_dtype vt, int64_t k, int64_t ldv, double* C,
+                 int64_t* nn_index, int32_t* nn_label, double* nn_dist2,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Optional phase timing for measurement tools.  Between rbd_profiler_begin and
  * rbd_profiler_end, every rbd_fit call made by the calling host thread records
  * HIP events on its stream around the launches of the phases selected by

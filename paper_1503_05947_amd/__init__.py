@@ -160,6 +160,56 @@ def project(Y, V, stream=None):
     return Tv, err
 
 
+@dataclass
+class Classification:
+    index: "object"       # (k,) int64 nearest training column
+    label: "object"       # (k,) int32 its label
+    dist2: "object"       # (k,) float64 squared distance in the compressed coordinates
+    C: "object"           # (d, k) float64 coordinates Y'V of the queries
+
+
+def classify(Y, T, V, labels=None, stream=None, sync: bool = True, workspace=None) -> Classification:
+    """Nearest training sample in compressed coordinates (rbd_classify): c = Y'v
+    for every column v of V, then argmin_j ||c - T(:, j)||^2 (lowest index on ties).
+
+    Y (m, d) and T (d, n) are float64 (typically a fit's basis and T); labels
+    is an int32 vector of n class labels or None.  With ``sync`` False the
+    call only enqueues on ``stream``; ``workspace`` may pass a reusable uint8
+    buffer of at least ``_lib.classify_workspace_size`` bytes."""
+    torch = _torch()
+    _check_matrix(Y, "Y")
+    _check_matrix(T, "T")
+    _check_matrix(V, "V")
+    if Y.dtype != torch.float64 or T.dtype != torch.float64:
+        raise TypeError("Y and T must be float64")
+    m, d = Y.shape
+    if T.shape[0] != d or V.shape[0] != m:
+        raise ValueError("shapes: Y (m, d), T (d, n), V (m, k)")
+    n, k = T.shape[1], V.shape[1]
+    dev = V.device
+    if labels is not None:
+        if labels.dtype != torch.int32 or labels.numel() != n or labels.device != dev or not labels.is_contiguous():
+            raise ValueError("labels must be a contiguous int32 vector of n values on V's device")
+    ws = _lib.classify_workspace_size(m, d, k)
+    if workspace is None or workspace.numel() < ws:
+        workspace = torch.empty(ws, dtype=torch.uint8, device=dev)
+    C = torch.empty((d, k), dtype=torch.float64, device=dev)
+    index = torch.empty(k, dtype=torch.int64, device=dev)
+    label = torch.empty(k, dtype=torch.int32, device=dev)
+    dist2 = torch.empty(k, dtype=torch.float64, device=dev)
+    lib = load()
+    with torch.cuda.device(dev):
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        rc = lib.rbd_classify(Y.data_ptr(), Y.stride(0), m, d, T.data_ptr(), T.stride(0), n,
+                              labels.data_ptr() if labels is not None else None, V.data_ptr(), dtype_code(V.dtype),
+                              k, V.stride(0), C.data_ptr(), index.data_ptr(), label.data_ptr(), dist2.data_ptr(),
+                              workspace.data_ptr(), workspace.numel(), s.cuda_stream)
+        _lib.check(rc, "rbd_classify")
+        if sync:
+            s.synchronize()
+    return Classification(index, label, dist2, C)
+
+
 # ---------------------------------------------------------------------------
 # batched fits
 # ---------------------------------------------------------------------------

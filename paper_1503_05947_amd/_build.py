@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librbd.so")
-SOURCES = ["rbd_api.hip", "rbd_batched.hip", "rbd_backward.hip"]
+SOURCES = ["rbd_api.hip", "rbd_batched.hip", "rbd_backward.hip", "rbd_classify.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

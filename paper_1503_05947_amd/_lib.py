@@ -35,6 +35,9 @@ SIGNATURES = {
     "rbd_batched_autotune": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _i32, _dp, ctypes.c_int, _i32, _i32,
                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "rbd_reconstruct": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, _i64, _i64, _vp, _i64, _vp]),
+    "rbd_classify_workspace_size": (ctypes.c_int, [_i64, _i32, _i64, ctypes.POINTER(_sz)]),
+    "rbd_classify": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, _i64, _i64, _vp, _vp, ctypes.c_int, _i64, _i64,
+                                    _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_reconstruct_backward_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "rbd_reconstruct_backward": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _vp, ctypes.c_int, _i64, _vp, _i64, _vp,
                                                 _i64, _vp, _i64, _i64, _i32, _vp, _i64, _vp, _sz, _vp]),
@@ -107,6 +110,12 @@ def fit_workspace_size(m: int, n: int, d_max: int, dtype: int) -> int:
 def project_workspace_size(m: int, d: int, k: int, dtype: int) -> int:
     out = ctypes.c_size_t(0)
     check(load().rbd_project_workspace_size(m, d, k, dtype, ctypes.byref(out)), "rbd_project_workspace_size")
+    return out.value
+
+
+def classify_workspace_size(m: int, d: int, k: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(load().rbd_classify_workspace_size(m, d, k, ctypes.byref(out)), "rbd_classify_workspace_size")
     return out.value
 
 

@@ -25,26 +25,10 @@ using namespace rbd;
 int64_t cd(int64_t a, int64_t b) { return (a + b - 1) / b; }
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-constexpr size_t kPartElems = (size_t)4 << 20;   // split-k partials: 32 MB
-
 template <bool TA, bool TB, typename TAe, typename TBe>
 hipError_t gemm(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda, const TBe* B, int64_t ldb,
                 double beta, double* C, int64_t ldc, double* part, size_t part_elems, hipStream_t s) {
-    const int64_t tiles = cd(M, kGM) * cd(N, kGN);
-    int64_t splits = 1;
-    while (part && tiles * splits < 512 && K / (splits * 2) >= 256 && (size_t)(splits * 2) * M * N <= part_elems)
-        splits *= 2;
-    const int64_t kchunk = cd(cd(K, splits), kGK) * kGK;
-    splits = std::max<int64_t>(1, cd(K, kchunk));
-    const dim3 grid((unsigned)cd(N, kGN), (unsigned)cd(M, kGM), (unsigned)splits);
-    gemm_f64_kernel<TA, TB, TAe, TBe><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                            splits > 1 ? part : nullptr);
-    if (splits > 1) {
-        const int64_t tot = M * N;
-        gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, cd(tot, 256)), 256, 0, s>>>(
-            M, N, (int)splits, alpha, part, beta, C, ldc);
-    }
-    return hipGetLastError();
+    return gemm_f64<TA, TB, TAe, TBe>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, part_elems, s);
 }
 
 // Rinv = R^{-1} (upper triangular, d x d row-major), R(i, k) = T(i, piv[k]) for i <= k.

@@ -13,6 +13,8 @@
 // summed in a fixed order by gemm_split_sum_kernel.
 #pragma once
 
+#include <algorithm>
+
 #include "rbd_device.h"
 
 namespace rbd {
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 }
 
 // C = alpha * sum_{s < splits} part[s] + beta * C (fixed order over s).
-__global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, int64_t N, int splits, double alpha,
+static __global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, int64_t N, int splits, double alpha,
                                                               const double* __restrict__ part, double beta,
                                                               double* __restrict__ C, int64_t ldc) {
     const int64_t tot = M * N;
@@ -111,6 +113,33 @@ __global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, int64_t 
         const double prev = beta != 0.0 ? C[i * ldc + j] : 0.0;
         C[i * ldc + j] = alpha * s + beta * prev;
     }
+}
+
+constexpr size_t kPartElems = (size_t)4 << 20;   // split-k partials: 32 MB
+
+// Host side: C = alpha op(A) op(B) + beta C.  The k range is split (partials
+// in `part`, at most part_elems doubles, summed in a fixed order) while the
+// output tiles alone would leave the GPU mostly idle.
+template <bool TA, bool TB, typename TAe, typename TBe>
+inline hipError_t gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda, const TBe* B,
+                           int64_t ldb, double beta, double* C, int64_t ldc, double* part, size_t part_elems,
+                           hipStream_t s) {
+    auto cdiv = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    const int64_t tiles = cdiv(M, kGM) * cdiv(N, kGN);
+    int64_t splits = 1;
+    while (part && tiles * splits < 512 && K / (splits * 2) >= 256 && (size_t)(splits * 2) * M * N <= part_elems)
+        splits *= 2;
+    const int64_t kchunk = cdiv(cdiv(K, splits), kGK) * kGK;
+    splits = std::max<int64_t>(1, cdiv(K, kchunk));
+    const dim3 grid((unsigned)cdiv(N, kGN), (unsigned)cdiv(M, kGM), (unsigned)splits);
+    gemm_f64_kernel<TA, TB, TAe, TBe><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                            splits > 1 ? part : nullptr);
+    if (splits > 1) {
+        const int64_t tot = M * N;
+        gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(tot, 256)), 256, 0, s>>>(
+            M, N, (int)splits, alpha, part, beta, C, ldc);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace rbd

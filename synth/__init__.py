@@ -413,7 +413,7 @@ class ViewClasses:
             lab = labels[q0:q0 + step].long()
             a = self.pose * torch.randn((lab.numel(), Md.shape[1]), generator=gen, device=dev,
                                         dtype=torch.float64)
-            V = Tm[lab] + torch.einsum("qi,qim->qm", a, Md[lab])
+            V = Tm[lab] + torch.bmm(a[:, None, :].contiguous(), Md[lab].contiguous())[:, 0, :]
             V += self.noise * torch.randn(V.shape, generator=gen, device=dev, dtype=torch.float64)
             out[:, q0:q0 + lab.numel()] = V.T.to(out.dtype)
 
