@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--backward", action="store_true",
                     help="also time the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
                          "fixed from a tol-0 fit, G ~ N(0,1)")
+    ap.add_argument("--classify", action="store_true",
+                    help="also time recognition of 262144 generated queries in compressed coordinates")
     ap.add_argument("--weighted", action="store_true",
                     help="also time the diagonal A-norm fit (disc of rows weighted 100x) on the FP32 field")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -327,6 +329,66 @@ def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True):
     return out
 
 
+def classify_section(rbd, K, W, k=262144, d_max=40, cpu=True):
+    """Recognition at scale: RBD of 200 training views (20 classes x 10, 112 x 92
+    grid, FP32), then k generated query views classified in compressed coordinates."""
+    import numpy as np
+    import torch
+
+    import synth
+    dev = torch.device("cuda:0")
+    vc = synth.view_classes(0)
+    Xtr, ytr, Xte, yte = vc.split()
+    m, n = Xtr.shape
+    log(f"classify: training fit {m} x {n}, d_max {d_max}; {k} queries")
+    Xd = torch.from_numpy(synth.quantize(Xtr, "f32")[0]).to(dev)
+    fit = rbd.fit(Xd, tol=0.0, d_max=d_max)
+    d = fit.d
+    Y = fit.Y.contiguous()
+    T = fit.T.contiguous()
+    labels = torch.from_numpy(ytr.astype(np.int32)).to(dev)
+    lab_q = torch.arange(k, dtype=torch.int32, device=dev) % len(vc.counts)
+    V = torch.empty((m, k), dtype=torch.float32, device=dev)
+    vc.fill_queries(V, lab_q, coeff_seed=1)
+    from paper_1503_05947_amd import _lib
+    ws = torch.empty(_lib.classify_workspace_size(m, d, k), dtype=torch.uint8, device=dev)
+    for _ in range(W):
+        res = rbd.classify(Y, T, V, labels=labels, sync=False, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        res = rbd.classify(Y, T, V, labels=labels, sync=False, workspace=ws)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / K
+    acc = (res.label == lab_q).double().mean().item()
+    flops = 2.0 * m * d * k
+    out = {"workload": f"view classes: 20 classes, {m} pixels (112 x 92), {n} training views, "
+                       f"{k} generated query views (FP32)", "d": d, "queries": k,
+           "value": round(k / sec, 1), "unit": "queries/s", "ms": round(sec * 1e3, 3),
+           "accuracy": round(acc, 4),
+           "projection_GFLOP": round(flops / 1e9, 1), "projection_TFLOPs": round(flops / sec / 1e12, 2),
+           "peak_TFLOPs_f64_matrix": 78.6, "frac": round(flops / sec / 78.6e12, 4),
+           "query_GB": round(m * k * 4 / 1e9, 2)}
+    if cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        sample = 4096
+        Vs = V[:, :sample].cpu().numpy().astype(np.float64)
+        Yh, Th = Y.cpu().numpy(), T.cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.rbd_classify(Yh, Th, ytr, Vs)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(sample / t, 1), "unit": "queries/s", "cores": int(cores),
+                               "kind": "oracle", "sample": f"the first {sample} queries ({t:.2f} s)"}
+    del V
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_cpu_baseline(count=4096, sample=24, d_max=128, tol=1e-6):
     import numpy as np
     import oracle
@@ -483,6 +545,9 @@ def main():
         out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup)
         if not args.no_cpu_baseline:
             out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
+    if args.classify:
+        torch.cuda.empty_cache()
+        out["classify"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
     if args.backward:
         torch.cuda.empty_cache()
         out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
