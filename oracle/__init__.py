@@ -90,20 +90,26 @@ def mgs_twice(v: np.ndarray, Y: np.ndarray, d: int) -> np.ndarray:
     return v
 
 
-def _anorm_cols(R: np.ndarray, w) -> np.ndarray:
-    """||r_j||_A = sqrt(r_j' A r_j) for A = diag(w) (w = None: the identity)."""
+def _anorm_cols(R: np.ndarray, w, A=None) -> np.ndarray:
+    """||r_j||_A = sqrt(r_j' A r_j) (section 3.2): A = diag(w), or a general
+    symmetric positive definite A (dense or scipy.sparse); both None: A = I."""
+    if A is not None:
+        q = np.einsum("ij,ij->j", R, np.asarray(A @ R))
+        return np.sqrt(np.maximum(q, 0.0))
     if w is None:
         return _colnorms(R)
     return np.sqrt(np.einsum("i,ij,ij->j", w, R, R))
 
 
-def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weights=None) -> OracleFit:
+def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weights=None, A=None) -> OracleFit:
     """Algorithm 1, (Y, T) = RBD(X, eps_R, d_max) (section 3.1).
 
     ``weights`` = None uses A = I; otherwise A = diag(weights) (the "general
-    diagonal" choice of section 3.2): the basis and T = Y'X are unchanged, and
-    every error of step 2.3 (and E_0, and the relative tolerance) is the
-    A-norm ||x_j - Y T(:, j)||_A of eq. (3), evaluated here by its definition.
+    diagonal" choice of section 3.2); ``A`` (dense or scipy.sparse, symmetric
+    positive definite) is the "general SPD" choice.  The basis and T = Y'X are
+    unchanged, and every error of step 2.3 (and E_0, and the relative
+    tolerance) is the A-norm ||x_j - Y T(:, j)||_A of eq. (3), evaluated here
+    by its definition on the explicit residual.
 
     ``X`` must already hold the stored values (e.g. FP32- or BF16-rounded data
     upcast to FP64).  Returns the first ``d`` basis vectors, rows of T, pivots,
@@ -122,8 +128,10 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weigh
     w = None if weights is None else np.asarray(weights, dtype=np.float64)
     if w is not None and (w.shape != (m,) or not np.all(w > 0) or not np.all(np.isfinite(w))):
         raise ValueError("weights must be m positive finite values")
+    if A is not None and (w is not None or A.shape != (m, m)):
+        raise ValueError("A must be m x m (and not combined with weights)")
     # pre-computation of diag(X'AX): the error of every column with d = 0
-    e = _anorm_cols(X, w)
+    e = _anorm_cols(X, w, A)
     E0 = float(e.max())
     tau = float(tol) * E0 if rel else float(tol)
 
@@ -159,7 +167,7 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weigh
         pivots.append(i)
         d += 1
         # 2.3: errors by their definition, pivots masked
-        e = _anorm_cols(R, w)
+        e = _anorm_cols(R, w, A)
         e[chosen] = 0.0
         E_cur = float(e.max())
         gap_hist.append(_gap(e[~chosen], E0) if (~chosen).sum() >= 2 else np.inf)
@@ -173,12 +181,17 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weigh
                      gap_hist=np.array(gap_hist), d=d, tau=tau, stop=stop)
 
 
-def eq3_error(x, Y, c, weights=None):
-    """eq. (3): ||v - Y c||_A^2 = v'Av - 2 c'Y'Av + c'Y'AYc for A = diag(weights)."""
+def eq3_error(x, Y, c, weights=None, A=None):
+    """eq. (3): ||v - Y c||_A^2 = v'Av - 2 c'Y'Av + c'Y'AYc for A = diag(weights)
+    or a given SPD matrix A (dense or scipy.sparse)."""
     x = np.asarray(x, dtype=np.float64)
-    w = np.ones(x.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64)
-    Av = w * x
-    AY = w[:, None] * Y
+    if A is not None:
+        Av = np.asarray(A @ x).ravel()
+        AY = np.asarray(A @ Y)
+    else:
+        w = np.ones(x.shape[0]) if weights is None else np.asarray(weights, dtype=np.float64)
+        Av = w * x
+        AY = w[:, None] * Y
     return float(x @ Av - 2.0 * c @ (Y.T @ Av) + c @ (Y.T @ AY) @ c)
 
 

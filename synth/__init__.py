@@ -438,3 +438,38 @@ def view_classes(seed: int = 0, classes: int = 20, rows: int = 112, cols: int = 
     modes = np.stack([np.stack([field() for _ in range(nmodes)]) for _ in range(classes)])
     counts = g.integers(lo, hi + 1, size=classes)
     return ViewClasses(templates, modes, counts, pose, noise, seed)
+
+
+def grid_laplacian_spd(rows: int, cols: int, c: float = 1.0):
+    """A = I + c L, L the 5-point graph Laplacian of a rows x cols grid
+    (row-major numbering): symmetric positive definite, an energy-type norm
+    for fields on the grid.  Returned as CSR arrays (indptr int64, indices
+    int32, data float64), sorted column indices per row."""
+    m = rows * cols
+    idx = np.arange(m).reshape(rows, cols)
+    deg = np.zeros((rows, cols))
+    pairs = []
+    if rows > 1:
+        pairs.append((idx[:-1, :].ravel(), idx[1:, :].ravel()))
+        deg[:-1, :] += 1
+        deg[1:, :] += 1
+    if cols > 1:
+        pairs.append((idx[:, :-1].ravel(), idx[:, 1:].ravel()))
+        deg[:, :-1] += 1
+        deg[:, 1:] += 1
+    r = [np.arange(m)]
+    cidx = [np.arange(m)]
+    v = [1.0 + c * deg.ravel()]
+    for a, b in pairs:
+        r += [a, b]
+        cidx += [b, a]
+        v += [np.full(a.size, -c), np.full(a.size, -c)]
+    r = np.concatenate(r)
+    cidx = np.concatenate(cidx)
+    v = np.concatenate(v)
+    order = np.lexsort((cidx, r))
+    r, cidx, v = r[order], cidx[order], v[order]
+    indptr = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(indptr, r + 1, 1)
+    indptr = np.cumsum(indptr)
+    return indptr, cidx.astype(np.int32), v.astype(np.float64)
