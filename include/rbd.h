@@ -56,7 +56,8 @@ enum {
     RBD_EINVAL = -1,      /* bad pointer, size, leading dimension or option      */
     RBD_ENONFINITE = -2,  /* X holds NaN or Inf (device status only)              */
     RBD_EWORKSPACE = -3,  /* workspace smaller than the size query returned       */
-    RBD_EDEVICE = -4      /* a HIP launch or runtime call failed                  */
+    RBD_EDEVICE = -4,     /* a HIP launch or runtime call failed                  */
+    RBD_EMATRIX = -5      /* sparse A: an index outside its rows (device status)  */
 };
 
 /* Why the greedy loop ended (written to stop_reason when non-NULL). */
@@ -130,6 +131,33 @@ int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t 
                      double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
                      int32_t* d_out, int32_t* status, int32_t* stop_reason,
                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rbd_fit_spd -- Algorithm 1 with the A-norm of section 3.2 for a general
+ * symmetric positive definite A ("preserve data across different entries
+ * anisotropically"), A given in CSR form:
+ *   a_indptr   m + 1 int64 row offsets into a_indices / a_values
+ *   a_indices  a_nnz int32 column indices in [0, m)
+ *   a_values   a_nnz FP64 values
+ * The basis Y and T = Y'X are built exactly as by rbd_fit; every error of step
+ * 2.3 (E_0, the relative tolerance, the argmax, col_err, err_hist) is
+ * ||x_j - Y T(:, j)||_A = sqrt(r' A r), eq. (3).  Symmetry and definiteness
+ * of A are the caller's responsibility; an index outside [0, m) or a row
+ * range outside [0, a_nnz) is skipped by every kernel and reported through
+ * *status as RBD_EMATRIX (d = 0).
+ * The errors are downdated as for a diagonal A with g = (I - YY')(A xi)
+ * (one sparse product per step).  Unlike rbd_fit, this entry point
+ * synchronises its stream once per greedy step: exact refreshes of queued
+ * columns materialise their residuals in chunks, and the host reads the
+ * queue length to launch them.  Other arguments, outputs and errors are
+ * those of rbd_fit; workspace: rbd_fit_spd_workspace_size() bytes.
+ */
+int rbd_fit_spd_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes);
+int rbd_fit_spd(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const int64_t* a_indptr,
+                const int32_t* a_indices, const double* a_values, int64_t a_nnz, double tol, rbd_tol_mode mode,
+                int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err,
+                double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * rbd_project_workspace_size -- bytes of workspace rbd_project needs.

@@ -62,14 +62,43 @@ class FitResult:
     stop: str
 
 
-class FitBuffers:
-    """Outputs and workspace of one rbd_fit configuration, reusable across calls."""
+@dataclass
+class CsrMatrix:
+    """A symmetric positive definite m x m matrix in CSR form, on the device:
+    indptr (m + 1, int64), indices (nnz, int32), values (nnz, float64)."""
+    indptr: "object"
+    indices: "object"
+    values: "object"
 
-    def __init__(self, m: int, n: int, d_max: int, dtype, device):
+    @property
+    def m(self) -> int:
+        return int(self.indptr.numel()) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.values.numel())
+
+    def check(self, m: int, device) -> None:
+        torch = _torch()
+        ok = (self.indptr.dtype == torch.int64 and self.indices.dtype == torch.int32
+              and self.values.dtype == torch.float64 and self.m == m and self.indices.numel() == self.nnz
+              and all(t.device == device and t.is_contiguous() and t.dim() == 1
+                      for t in (self.indptr, self.indices, self.values)))
+        if not ok:
+            raise ValueError("A must be CSR on X's device: indptr int64 (m + 1), indices int32, values float64")
+
+
+class FitBuffers:
+    """Outputs and workspace of one rbd_fit configuration, reusable across calls
+    (``spd``: sized for rbd_fit_spd as well)."""
+
+    def __init__(self, m: int, n: int, d_max: int, dtype, device, spd: bool = False):
         torch = _torch()
         self.m, self.n, self.d_max, self.dtype = int(m), int(n), int(d_max), dtype
         code = dtype_code(dtype)
-        self.ws_bytes = _lib.fit_workspace_size(self.m, self.n, self.d_max, code)
+        self.spd = bool(spd)
+        self.ws_bytes = (_lib.fit_spd_workspace_size if spd else _lib.fit_workspace_size)(
+            self.m, self.n, self.d_max, code)
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
         self.Y = torch.empty((self.m, self.d_max), **f64)
@@ -82,6 +111,8 @@ class FitBuffers:
 
     def result(self) -> FitResult:
         d, status, stop = (int(v) for v in self.ints[:3].tolist())
+        if status == _lib.RBD_EMATRIX:
+            raise ValueError(f"rbd_fit_spd: {status_string(status)}")
         if status != _lib.RBD_OK:
             raise FloatingPointError(f"rbd_fit: {status_string(status)}")
         return FitResult(Y=self.Y[:, :d], T=self.T[:d], pivots=self.pivots[:d], col_err=self.col_err,
@@ -89,9 +120,10 @@ class FitBuffers:
 
 
 def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: int = -1, stream=None,
-             weights=None) -> None:
-    """Enqueue rbd_fit (or rbd_fit_weighted when ``weights`` is given: A = diag(weights))
-    on ``stream`` (default: torch's current stream) without waiting."""
+             weights=None, A: "CsrMatrix | None" = None) -> None:
+    """Enqueue rbd_fit (rbd_fit_weighted when ``weights`` is given: A = diag(weights);
+    rbd_fit_spd when a CsrMatrix ``A`` is given) on ``stream`` (default: torch's
+    current stream).  Only the SPD variant waits (once per greedy step)."""
     torch = _torch()
     _check_matrix(X, "X")
     if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
@@ -108,7 +140,16 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
         outs = (bufs.Y.data_ptr(), bufs.T.data_ptr(), bufs.pivots.data_ptr(), bufs.col_err.data_ptr(),
                 bufs.err_hist.data_ptr(), ints, ints + 4, ints + 8, bufs.workspace.data_ptr(),
                 bufs.workspace.numel(), s.cuda_stream)
-        if weights is None:
+        if A is not None:
+            if weights is not None:
+                raise ValueError("give weights or A, not both")
+            if not bufs.spd:
+                raise ValueError("buffers were not sized for a sparse A (FitBuffers(..., spd=True))")
+            A.check(bufs.m, X.device)
+            rc = lib.rbd_fit_spd(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), A.indptr.data_ptr(),
+                                 A.indices.data_ptr(), A.values.data_ptr(), A.nnz, float(tol), mode, bufs.d_max,
+                                 int(start), *outs)
+        elif weights is None:
             rc = lib.rbd_fit(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol), mode,
                              bufs.d_max, int(start), *outs)
         else:
@@ -118,17 +159,18 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
 
 
 def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1, stream=None,
-        weights=None) -> FitResult:
+        weights=None, A: "CsrMatrix | None" = None) -> FitResult:
     """Algorithm 1 on a device matrix X (m x n, f32/bf16/f16/f64 storage).
 
     ``tol`` is eps_R (absolute, or relative to max_j ||x_j|| when ``rel``);
     ``start < 0`` starts from the column of largest norm; ``weights`` (float64,
-    m values > 0) selects the diagonal A-norm of section 3.2.  Waits for the
+    m values > 0) selects the diagonal A-norm of section 3.2, ``A`` (CsrMatrix)
+    a general SPD A-norm.  Waits for the
     device and returns views of the first d basis vectors / rows of T.
     """
     torch = _torch()
-    bufs = FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
-    fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream, weights=weights)
+    bufs = FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device, spd=A is not None)
+    fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream, weights=weights, A=A)
     (stream or torch.cuda.current_stream(X.device)).synchronize()
     return bufs.result()
 

@@ -12,7 +12,7 @@ RBD_F32, RBD_BF16, RBD_F16, RBD_F64 = 0, 1, 2, 3
 # rbd_tol_mode
 RBD_TOL_ABS, RBD_TOL_REL = 0, 1
 # status codes
-RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE = 0, -1, -2, -3, -4
+RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE, RBD_EMATRIX = 0, -1, -2, -3, -4, -5
 # stop reasons
 RBD_STOP_TOL, RBD_STOP_DMAX, RBD_STOP_BREAK = 1, 2, 3
 RBD_MAX_D = 1024
@@ -26,6 +26,9 @@ SIGNATURES = {
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_fit_weighted": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32, _i64,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbd_fit_spd_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.POINTER(_sz)]),
+    "rbd_fit_spd": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _dp, ctypes.c_int, _i32,
+                                   _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_project_workspace_size": (ctypes.c_int, [_i64, _i32, _i64, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_project": (ctypes.c_int, [_vp, _i64, _i64, _i32, _vp, ctypes.c_int, _i64, _i64, _vp, _vp,
                                    _vp, _sz, _vp]),
@@ -110,6 +113,12 @@ def fit_workspace_size(m: int, n: int, d_max: int, dtype: int) -> int:
 def project_workspace_size(m: int, d: int, k: int, dtype: int) -> int:
     out = ctypes.c_size_t(0)
     check(load().rbd_project_workspace_size(m, d, k, dtype, ctypes.byref(out)), "rbd_project_workspace_size")
+    return out.value
+
+
+def fit_spd_workspace_size(m: int, n: int, d_max: int, dtype: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(load().rbd_fit_spd_workspace_size(m, n, d_max, dtype, ctypes.byref(out)), "rbd_fit_spd_workspace_size")
     return out.value
 
 

@@ -497,6 +497,200 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
 }
 
 // ---------------------------------------------------------------------------
+// General SPD A (section 3.2) in CSR form.  Same loop as the diagonal case,
+// with A xi from a sparse product.  Exact refreshes need the residual columns
+// themselves (r' A r), so they run in chunks whose number depends on how many
+// columns are queued: the host reads the loop state after each step's update
+// (one stream synchronisation per step) and launches exactly those chunks.
+// ---------------------------------------------------------------------------
+struct SpdPlan {
+    FitPlan F;
+    int q_rows = 0, q_S = 0, cq = 0;
+    size_t o_u, o_rbuf, o_qpart, total;
+};
+
+bool make_spd_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, SpdPlan* P) {
+    if (!make_fit_plan(m, n, d_max, xt, &P->F)) return false;
+    P->q_rows = (int)std::max<int64_t>(64, cdiv(m, 2048));
+    P->q_S = (int)cdiv(m, P->q_rows);
+    // residual chunk: about 512 MB of FP64 columns, 64 .. 1024 of them
+    int64_t c = ((int64_t)1 << 29) / (8 * m);
+    c = std::max<int64_t>(64, std::min<int64_t>(1024, c / 64 * 64));
+    c = std::min<int64_t>(c, cdiv(n, 64) * 64);
+    P->cq = (int)c;
+    size_t o = P->F.total;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    P->o_u = take(8 * (size_t)m);
+    P->o_rbuf = take(8 * (size_t)m * P->cq);
+    P->o_qpart = take(8 * (size_t)P->q_S * n);
+    P->total = o;
+    return true;
+}
+
+template <int KC>
+void launch_ytu(const FitPlan& P, const double* Y, const State* st, int d, const double* u, const double* v2,
+                double* part, hipStream_t s) {
+    ytu_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, u, v2, part,
+                                                               std::max(P.D, 1));
+}
+
+template <typename Tx>
+int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol, int rel, int64_t start, double* Y,
+                  double* T, int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
+                  int32_t* stop_reason, char* ws, hipStream_t s) {
+    const FitPlan& P = Q.F;
+    State* st = reinterpret_cast<State*>(ws + P.o_state);
+    unsigned* tickets = reinterpret_cast<unsigned*>(ws + P.o_tickets);
+    double* e2 = reinterpret_cast<double*>(ws + P.o_e2);
+    double* base2 = reinterpret_cast<double*>(ws + P.o_base2);
+    int* flist = reinterpret_cast<int*>(ws + P.o_flist);
+    double* bres_v = reinterpret_cast<double*>(ws + P.o_bres_v);
+    int64_t* bres_i = reinterpret_cast<int64_t*>(ws + P.o_bres_i);
+    double* v1 = reinterpret_cast<double*>(ws + P.o_v1);
+    double* v2 = reinterpret_cast<double*>(ws + P.o_v2);
+    double* h2 = reinterpret_cast<double*>(ws + P.o_h2);
+    double* part = reinterpret_cast<double*>(ws + P.o_part);
+    double* l2 = reinterpret_cast<double*>(ws + P.o_l2);
+    double* g = reinterpret_cast<double*>(ws + P.o_g);
+    double* hw = reinterpret_cast<double*>(ws + P.o_hw);
+    double* xp = reinterpret_cast<double*>(ws + P.o_xp);
+    double* u = reinterpret_cast<double*>(ws + Q.o_u);
+    double* rbuf = reinterpret_cast<double*>(ws + Q.o_rbuf);
+    double* qpart = reinterpret_cast<double*>(ws + Q.o_qpart);
+    const int64_t nw = 2 * P.n;
+    const int N = Ld<Tx>::N;
+    const int vec_ok = (ldx % N == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    const bool nt = (double)P.m * (double)ldx * sizeof(Tx) > 512.0 * 1024 * 1024;
+
+    prof_fit_begin(s);
+    init_state_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(P.ntickets, 256))), 256, 0, s>>>(
+        st, tickets, P.ntickets, P.D);
+    RBD_LAUNCH_CHECK();
+    // pre-computation of diag(X'AX) (section 3.3)
+    prof_begin(RBD_PHASE_COLNORM, s);
+    csr_xax_kernel<Tx><<<dim3((unsigned)cdiv(P.n, 256), (unsigned)P.sc_S), 256, 0, s>>>(X, ldx, P.m, P.n, A, P.sc_rows,
+                                                                                       part, st);
+    RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_COLNORM, s);
+    prof_begin(RBD_PHASE_INIT, s);
+    const int up_per = (int)cdiv(P.sc_S, P.up_SG);
+    const int up_groups = (int)cdiv(P.sc_S, up_per);
+    reduce_rows_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)up_groups), 256, 0, s>>>(nullptr, part, P.n, P.sc_S,
+                                                                                          up_per, P.n, l2, P.n);
+    RBD_LAUNCH_CHECK();
+    update_kernel<kInit><<<P.up_ncb, 256, 0, s>>>(P.n, st, 0, l2, up_groups, tickets, e2, base2, T, P.n, flist,
+                                                  bres_v, bres_i, pivots, err_hist, start, tol, rel);
+    RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_INIT, s);
+
+    for (int d = 0; d < P.D; ++d) {
+        const int kc = kc_for(d);
+        prof_begin(RBD_PHASE_CGS1, s);
+        launch_gather<Tx>(P, X, ldx, st, xp, s);
+        switch (kc) {
+            case 1: launch_cgs1<1>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 2: launch_cgs1<2>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 4: launch_cgs1<4>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 8: launch_cgs1<8>(P, xp, Y, T, st, d, v1, part, s); break;
+            default: launch_cgs1<16>(P, xp, Y, T, st, d, v1, part, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        if (d > 0) {
+            launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, h2, 0, s);
+            RBD_LAUNCH_CHECK();
+        }
+        prof_end(RBD_PHASE_CGS1, s);
+        prof_begin(RBD_PHASE_CGS2, s);
+        switch (kc) {
+            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S, 0);
+        RBD_LAUNCH_CHECK();
+        // u = A v2; hw = Y'u and v2'u; g = P_d(A xi); ||xi||_A^2
+        spmv_kernel<<<(unsigned)std::min<int64_t>(16384, cdiv(P.m, 256)), 256, 0, s>>>(st, A, P.m, v2, u);
+        RBD_LAUNCH_CHECK();
+        switch (kc) {
+            case 1: launch_ytu<1>(P, Y, st, d, u, v2, part, s); break;
+            case 2: launch_ytu<2>(P, Y, st, d, u, v2, part, s); break;
+            case 4: launch_ytu<4>(P, Y, st, d, u, v2, part, s); break;
+            case 8: launch_ytu<8>(P, Y, st, d, u, v2, part, s); break;
+            default: launch_ytu<16>(P, Y, st, d, u, v2, part, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, hw, 0, s);
+        RBD_LAUNCH_CHECK();
+        set_wxx_kernel<<<1, 64, 0, s>>>(st, hw, d);
+        RBD_LAUNCH_CHECK();
+        switch (kc) {
+            case 1: launch_gvec<1>(P, Y, st, d, u, nullptr, hw, g, s); break;
+            case 2: launch_gvec<2>(P, Y, st, d, u, nullptr, hw, g, s); break;
+            case 4: launch_gvec<4>(P, Y, st, d, u, nullptr, hw, g, s); break;
+            case 8: launch_gvec<8>(P, Y, st, d, u, nullptr, hw, g, s); break;
+            default: launch_gvec<16>(P, Y, st, d, u, nullptr, hw, g, s); break;
+        }
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_CGS2, s);
+        prof_begin(RBD_PHASE_XSCAN, s);
+        launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s, g);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_XSCAN, s);
+        prof_begin(RBD_PHASE_UPDATE, s);
+        reduce_rows_kernel<<<dim3((unsigned)cdiv(nw, 256), (unsigned)up_groups), 256, 0, s>>>(st, part, nw, P.sc_S,
+                                                                                             up_per, nw, l2, nw);
+        RBD_LAUNCH_CHECK();
+        update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flist,
+                                                       bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_UPDATE, s);
+        // the number of queued columns decides the refresh launches
+        State h;
+        if (hipMemcpyAsync(&h, st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess) return RBD_EDEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) return RBD_EDEVICE;
+        if (h.stop) break;
+        prof_begin(RBD_PHASE_RESID, s);
+        if (h.nflag > 0) {
+            for (int c0 = 0; c0 < h.nflag; c0 += Q.cq) {
+                const int cc = std::min(Q.cq, h.nflag - c0);
+                const unsigned grid = (unsigned)std::min<int64_t>(2048, cdiv(cc, 64) * P.rc_S);
+                resid_mfma_kernel<Tx, true><<<grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist + c0,
+                                                                  nullptr, cc, P.rc_rows, P.rc_S, nullptr, 0, nullptr,
+                                                                  rbuf, Q.cq);
+                RBD_LAUNCH_CHECK();
+                csr_quad_kernel<<<dim3((unsigned)cdiv(cc, 64), (unsigned)Q.q_S), 64, 0, s>>>(rbuf, Q.cq, P.m, cc, A,
+                                                                                          Q.q_rows, qpart, P.n, c0);
+                RBD_LAUNCH_CHECK();
+            }
+        }
+        prof_end(RBD_PHASE_RESID, s);
+        prof_begin(RBD_PHASE_RESID_FINISH, s);
+        if (h.nflag > 0) {
+            resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, qpart, P.n, Q.q_S, flist, e2, base2, P.n, tickets,
+                                                          pivots, err_hist, d);
+            RBD_LAUNCH_CHECK();
+        }
+        prof_end(RBD_PHASE_RESID_FINISH, s);
+        prof_step(s);
+    }
+    const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
+    const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
+    prof_begin(RBD_PHASE_EPILOGUE, s);
+    epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
+                                       stop_reason);
+    RBD_LAUNCH_CHECK();
+    prof_end(RBD_PHASE_EPILOGUE, s);
+    return RBD_OK;
+}
+
+// ---------------------------------------------------------------------------
 struct ProjPlan {
     int S = 1, rows = 0;
     int rc_rows = 0, rc_S = 0, rc_grid = 0;
@@ -609,6 +803,51 @@ int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t 
                      stop_reason, workspace, workspace_bytes, stream, weights);
 }
 
+int rbd_fit_spd_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes) {
+    if (!bytes) return RBD_EINVAL;
+    SpdPlan Q;
+    if (!make_spd_plan(m, n, d_max, xt, &Q)) return RBD_EINVAL;
+    *bytes = Q.total;
+    return RBD_OK;
+}
+
+int rbd_fit_spd(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const int64_t* a_indptr,
+                const int32_t* a_indices, const double* a_values, int64_t a_nnz, double tol, rbd_tol_mode mode,
+                int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err,
+                double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    SpdPlan Q;
+    if (!make_spd_plan(m, n, d_max, xt, &Q)) return RBD_EINVAL;
+    if (m >= (int64_t)INT32_MAX) return RBD_EINVAL;
+    if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status || !workspace) return RBD_EINVAL;
+    if (!a_indptr || (a_nnz > 0 && (!a_indices || !a_values)) || a_nnz < 0) return RBD_EINVAL;
+    if (ldx < n) return RBD_EINVAL;
+    if (!(tol >= 0.0) || tol == HUGE_VAL) return RBD_EINVAL;
+    if (mode != RBD_TOL_ABS && mode != RBD_TOL_REL) return RBD_EINVAL;
+    if (start >= n) return RBD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return RBD_EINVAL;
+    if (workspace_bytes < Q.total) return RBD_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = reinterpret_cast<char*>(workspace);
+    const int rel = (mode == RBD_TOL_REL);
+    const Csr A{a_indptr, a_indices, a_values, a_nnz};
+    switch (xt) {
+        case RBD_F32:
+            return fit_spd_typed<float>(Q, static_cast<const float*>(X), ldx, A, tol, rel, start, Y, T, pivots,
+                                        col_err, err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_F64:
+            return fit_spd_typed<double>(Q, static_cast<const double*>(X), ldx, A, tol, rel, start, Y, T, pivots,
+                                         col_err, err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_BF16:
+            return fit_spd_typed<bf16_t>(Q, static_cast<const bf16_t*>(X), ldx, A, tol, rel, start, Y, T, pivots,
+                                         col_err, err_hist, d_out, status, stop_reason, ws, s);
+        case RBD_F16:
+            return fit_spd_typed<f16_t>(Q, static_cast<const f16_t*>(X), ldx, A, tol, rel, start, Y, T, pivots,
+                                        col_err, err_hist, d_out, status, stop_reason, ws, s);
+    }
+    return RBD_EINVAL;
+}
+
 int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes) {
     if (!bytes || elem_bytes(vt) == 0) return RBD_EINVAL;
     ProjPlan P;
@@ -692,6 +931,7 @@ const char* rbd_status_string(int code) {
         case RBD_ENONFINITE: return "input holds a non-finite value";
         case RBD_EWORKSPACE: return "workspace too small";
         case RBD_EDEVICE: return "HIP launch or runtime error";
+        case RBD_EMATRIX: return "sparse A holds an index outside its rows";
     }
     return "unknown status";
 }

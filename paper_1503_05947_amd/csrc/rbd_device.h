@@ -26,11 +26,11 @@ struct State {
     int d;          // basis vectors accepted so far
     int p;          // column to orthonormalise at the next step
     int stop;       // 0 while running, else an RBD_STOP_* value
-    int status;     // RBD_OK or RBD_ENONFINITE
+    int status;     // RBD_OK, RBD_ENONFINITE or RBD_EMATRIX
     int nflag;      // columns queued for an exact error evaluation this step
     int D;          // min(d_max, m, n)
     int nonfinite;  // set while the column norms are formed
-    int pad0;
+    int bad_index;  // set when a sparse A holds an index out of range
     double tau;     // eps_R after the relative/absolute reading
     double E0;      // max_j ||x_j||
     double nu;      // ||v|| after the second Gram-Schmidt pass

@@ -54,7 +54,7 @@ __global__ void init_state_kernel(State* st, unsigned* tickets, int ntickets, in
     for (int64_t i = gid; i < ntickets; i += stride) tickets[i] = 0u;
     if (gid == 0) {
         st->d = 0; st->p = 0; st->stop = 0; st->status = RBD_OK; st->nflag = 0; st->D = D;
-        st->nonfinite = 0; st->pad0 = 0;
+        st->nonfinite = 0; st->bad_index = 0;
         st->tau = 0.0; st->E0 = 0.0; st->nu = 0.0; st->inv_nu = 0.0; st->wxx = 0.0; st->pad1 = 0.0;
     }
 }
@@ -276,7 +276,12 @@ __global__ __launch_bounds__(256) void update_kernel(int64_t n, State* __restric
         int64_t i = INT64_MAX;
         for (int c = 0; c < ncb; ++c) argmax_merge(v, i, bres_v[c], bres_i[c]);
         if (MODE == kInit) {
-            if (st->nonfinite) {
+            if (st->bad_index) {
+                st->status = RBD_EMATRIX;
+                st->stop = kStopError;
+                st->E0 = NAN;
+                err_hist[0] = NAN;
+            } else if (st->nonfinite) {
                 st->status = RBD_ENONFINITE;
                 st->stop = kStopError;
                 st->E0 = NAN;
@@ -470,8 +475,9 @@ __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y,
 }
 
 // ---------------------------------------------------------------------------
-// gvec (diagonal A): g = (w . v2 - Y hw) / nu, hw = Y'(w . v2), i.e.
-// g = P_{d}(A xi) with P_d the projector onto the complement of span(Y).
+// gvec: g = (A v2 - Y hw) / nu, hw = Y'(A v2), i.e. g = P_d(A xi) with P_d
+// the projector onto the complement of span(Y).  A v2 is w . v2 for a
+// diagonal A (w given), else passed in v2 itself (w = nullptr).
 // Then g' x_j drives the weighted downdate of the errors.
 // ---------------------------------------------------------------------------
 template <int KC, int RU>
@@ -510,7 +516,10 @@ __global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y,
         wave_sum_n<RU>(dot);
 #pragma unroll
         for (int u = 0; u < RU; ++u)
-            if (lane == u && rb + u < r1) g[rb + u] = (w[rb + u] * v2[rb + u] - dot[u]) * inv;
+            if (lane == u && rb + u < r1) {
+                const double av = w ? w[rb + u] * v2[rb + u] : v2[rb + u];   // w = nullptr: v2 holds A v2
+                g[rb + u] = (av - dot[u]) * inv;
+            }
     }
 }
 
@@ -758,7 +767,8 @@ __global__ __launch_bounds__(256) void reduce_rows_kernel(const State* __restric
 }
 
 // ---------------------------------------------------------------------------
-// resid_mfma: partial squared residual norms of listed columns,
+// resid_mfma: partial squared residual norms of listed columns (STORE:
+// the residual entries themselves, R[i * ldr + jj], instead of any sums),
 //   part[s * ldp + jj] = sum_{i in slab s} w_i (X[i, c] - sum_{k<K} Y[i, k] C[k, c])^2,
 // c = J ? J[jj] : jj, w_i = 1 without weights, for jj < count (count =
 // *count_dev when given, else count_host).  Work items (column tile, slab)
@@ -775,14 +785,15 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr bool kResidPrefetchX = false;    // load the tile's X entries before the products (measured: slower, spills)
 #define RBD_RESID_MIN_BLOCKS 2                // workgroups per CU the register budget is sized for
 
-template <typename Tx>
+template <typename Tx, bool STORE = false>
 __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
                                                           const double* __restrict__ Y, int64_t ldy, int K,
                                                           const double* __restrict__ C, int64_t ldc,
                                                           const int* __restrict__ J,
                                                           const int* __restrict__ count_dev, int count_host,
                                                           int rows_per_slab, int nslab, double* __restrict__ part,
-                                                          int64_t ldp, const double* __restrict__ w) {
+                                                          int64_t ldp, const double* __restrict__ w,
+                                                          double* __restrict__ R = nullptr, int64_t ldr = 0) {
     const int cnt = count_dev ? *count_dev : count_host;
     if (cnt == 0) return;
     constexpr int TM = 128, TN = 64, KB = 16;
@@ -888,11 +899,13 @@ __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(c
                             const double xv = kResidPrefetchX ? Ld<Tx>::from(xr[a][b][r])
                                                               : Ld<Tx>::one(X + row * ldx + col);
                             const double d = xv - acc[a][b][r];
-                            rs[b] = w ? fma(w[row] * d, d, rs[b]) : fma(d, d, rs[b]);
+                            if (STORE) R[row * ldr + t * TN + 16 * b + lr] = d;
+                            else rs[b] = w ? fma(w[row] * d, d, rs[b]) : fma(d, d, rs[b]);
                         }
                     }
             }
         }
+        if (STORE) continue;
         // column cc = 16 b + lane % 16: sum the four lane groups, then the four waves
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -941,6 +954,145 @@ __global__ __launch_bounds__(256) void resid_finish_kernel(State* __restrict__ s
         finish_step(st, d, v, i, pivots, err_hist);
         st->nflag = 0;
     }
+}
+
+// ---------------------------------------------------------------------------
+// General SPD A (section 3.2), A in CSR form (indptr int64, indices int32,
+// values FP64).  Every entry index is checked: an index outside [0, m) or
+// [0, nnz) is skipped and raises bad_index (reported as RBD_EMATRIX by the
+// set-up step, which reads every entry once).
+// ---------------------------------------------------------------------------
+struct Csr {
+    const int64_t* __restrict__ ip;
+    const int32_t* __restrict__ ix;
+    const double* __restrict__ av;
+    int64_t nnz;
+};
+
+__device__ __forceinline__ void csr_row(const Csr& A, int64_t i, int64_t& e0, int64_t& e1) {
+    e0 = max((int64_t)0, A.ip[i]);
+    e1 = min(A.nnz, A.ip[i + 1]);
+}
+
+// csr_xax: per row slab, part[slab * n + j] = sum_{i in slab} x_ij (A x_j)_i,
+// so that summing the slabs gives x_j' A x_j (the pre-computation of
+// diag(X'AX) in section 3.3).  One column per thread; all lanes walk the same
+// row of A (uniform loads).
+template <typename Tx>
+__global__ __launch_bounds__(256) void csr_xax_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                                                       Csr A, int rows_per_slab, double* __restrict__ part,
+                                                       State* __restrict__ st) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t jc = j < n ? j : n - 1;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab, r1 = min(m, r0 + (int64_t)rows_per_slab);
+    double acc = 0.0;
+    bool bad = false;
+    for (int64_t i = r0; i < r1; ++i) {
+        int64_t e0, e1;
+        csr_row(A, i, e0, e1);
+        double y = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t k = A.ix[e];
+            if (k < 0 || k >= m) { bad = true; continue; }
+            y = fma(A.av[e], Ld<Tx>::one(X + k * ldx + jc), y);
+        }
+        acc = fma(Ld<Tx>::one(X + i * ldx + jc), y, acc);
+    }
+    if (bad && threadIdx.x == 0) atomicOr(&st->bad_index, 1);
+    if (j < n) part[(int64_t)blockIdx.y * n + j] = acc;
+}
+
+// spmv: u = A v (one row per thread)
+__global__ __launch_bounds__(256) void spmv_kernel(const State* __restrict__ st, Csr A, int64_t m,
+                                                    const double* __restrict__ v, double* __restrict__ u) {
+    if (st->stop) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        int64_t e0, e1;
+        csr_row(A, i, e0, e1);
+        double y = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t k = A.ix[e];
+            if (k >= 0 && k < m) y = fma(A.av[e], v[k], y);
+        }
+        u[i] = y;
+    }
+}
+
+// ytu: per block, part[blk * ldp + k] = sum_i Y[i, k] u_i (k < d) and
+// part[blk * ldp + d] = sum_i v2_i u_i -- the inputs of g = P_d(A xi) and of
+// ||xi||_A^2.  Same row layout as the Gram-Schmidt passes.
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void ytu_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                   const State* __restrict__ st, int d, int rows_per_blk,
+                                                   const double* __restrict__ u, const double* __restrict__ v2,
+                                                   double* __restrict__ part, int64_t ldp) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double accs[KW];
+    __shared__ double sred[4];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) accs[k] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    double s = 0.0;
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+#pragma unroll
+        for (int q = 0; q < RU; ++q) {
+            const int64_t r = rb + q;
+            const bool ok = r < r1;
+            const double ur = ok ? u[r] : 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                if (ok && k < d) acc[c] = fma(Y[r * ldy + k], ur, acc[c]);
+            }
+            if (lane == q && ok) s = fma(v2[r], ur, s);
+        }
+    }
+    const double st2 = block_sum(s, sred);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = st2;
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (wv == q) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += acc[c];
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
+}
+
+// wxx = ||xi||_A^2 = (v2' A v2) / nu^2, from hw[d] = v2' u
+__global__ void set_wxx_kernel(State* __restrict__ st, const double* __restrict__ hw, int d) {
+    if (st->stop) return;
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->wxx = hw[d] * st->inv_nu * st->inv_nu;
+}
+
+// csr_quad: part[slab * ldp + c0 + jj] = sum_{i in slab} r_i,jj (A r_jj)_i for
+// the residual columns jj < cnt held in R (m x cnt, leading dimension ldr).
+__global__ __launch_bounds__(64) void csr_quad_kernel(const double* __restrict__ R, int64_t ldr, int64_t m, int cnt,
+                                                       Csr A, int rows_per_slab, double* __restrict__ part,
+                                                       int64_t ldp, int c0) {
+    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jc = jj < cnt ? jj : cnt - 1;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab, r1 = min(m, r0 + (int64_t)rows_per_slab);
+    double acc = 0.0;
+    for (int64_t i = r0; i < r1; ++i) {
+        int64_t e0, e1;
+        csr_row(A, i, e0, e1);
+        double y = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t k = A.ix[e];
+            if (k >= 0 && k < m) y = fma(A.av[e], R[k * ldr + jc], y);
+        }
+        acc = fma(R[i * ldr + jc], y, acc);
+    }
+    if (jj < cnt) part[(int64_t)blockIdx.y * ldp + c0 + jj] = acc;
 }
 
 // ---------------------------------------------------------------------------

@@ -21,9 +21,11 @@ def separated_prefix(ref, gap: float) -> int:
     return ref.d
 
 
-def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: bool = True, weights=None):
+def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: bool = True, weights=None,
+                norms=None):
     """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values;
-    weights: the diagonal of A when the errors are A-norms (eq. (3)), else None."""
+    weights: the diagonal of A when the errors are A-norms (eq. (3)), else None;
+    norms: a callable giving the column A-norms of a matrix, for a general A."""
     msgs = []
     E0 = ref.err_hist[0]
     k = min(separated_prefix(ref, gap), dev["d"], ref.d)
@@ -54,24 +56,26 @@ def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: boo
         msgs.append(f"d differs after a fully separated run: {dev['d']} vs {ref.d}")
     if dev["d"] == ref.d and abs(dev["err_hist"][dev["d"]] - ref.err_hist[ref.d]) > rtol * E0:
         msgs.append("final error differs: %.6e vs %.6e" % (dev["err_hist"][dev["d"]], ref.err_hist[ref.d]))
-    msgs += invariant_msgs(dev, X, rtol, weights=weights)
+    msgs += invariant_msgs(dev, X, rtol, weights=weights, norms=norms)
     return msgs
 
 
-def _norms(R, weights):
+def _norms(R, weights, norms=None):
+    if norms is not None:
+        return norms(R)
     if weights is None:
         return np.linalg.norm(R, axis=0)
     return np.sqrt(np.asarray(weights, dtype=np.float64) @ (R * R))
 
 
-def invariant_msgs(dev, X, rtol=1e-5, weights=None):
+def invariant_msgs(dev, X, rtol=1e-5, weights=None, norms=None):
     """Checks a device fit on its own: orthonormal Y, T = Y'X, certified errors, monotone history
     (with A = I: a Euclidean projection residual can grow in another A-norm)."""
     msgs = []
     d = dev["d"]
     Y, T = dev["Y"][:, :d], dev["T"][:d]
     nx = np.linalg.norm(X, axis=0)
-    E0 = _norms(X, weights).max()
+    E0 = _norms(X, weights, norms).max()
     if d:
         o = np.max(np.abs(Y.T @ Y - np.eye(d)))
         if o > 1e-12:
@@ -79,14 +83,14 @@ def invariant_msgs(dev, X, rtol=1e-5, weights=None):
         dt = np.max(np.abs(T - Y.T @ X))
         if dt > 1e-12 * max(nx.max(), 1e-300) * np.sqrt(X.shape[0]):
             msgs.append(f"T != Y'X ({dt:.2e})")
-    true_err = _norms(X - Y @ T, weights)
+    true_err = _norms(X - Y @ T, weights, norms)
     if d:
         true_err[dev["pivots"][:d]] = 0.0
     de = np.max(np.abs(true_err - dev["col_err"]))
     if de > rtol * max(E0, 1e-300):
         msgs.append(f"col_err not the true residual norm ({de / max(E0, 1e-300):.2e} E0)")
     h = dev["err_hist"][: d + 1]
-    if weights is None and np.any(np.diff(h) > 1e-9 * max(E0, 1e-300)):
+    if weights is None and norms is None and np.any(np.diff(h) > 1e-9 * max(E0, 1e-300)):
         msgs.append("error history increases")
     if len(set(dev["pivots"][:d].tolist())) != d:
         msgs.append("repeated pivot")

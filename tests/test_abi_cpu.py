@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_version_and_status_strings(lib):
     assert lib.rbd_version().decode().startswith("rbd-gfx950")
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert lib.rbd_status_string(code)
     assert lib.rbd_status_string(123) == b"unknown status"
 
