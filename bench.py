@@ -56,6 +56,8 @@ def parse():
                          "fixed from a tol-0 fit, G ~ N(0,1)")
     ap.add_argument("--classify", action="store_true",
                     help="also time recognition of 262144 generated queries in compressed coordinates")
+    ap.add_argument("--spd", action="store_true",
+                    help="also time the general SPD A-norm fit (A = I + grid Laplacian) on the FP32 field")
     ap.add_argument("--weighted", action="store_true",
                     help="also time the diagonal A-norm fit (disc of rows weighted 100x) on the FP32 field")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -531,6 +533,31 @@ def main():
         if args.phases:
             out["weighted"]["phases"] = phase_breakdown(rbd, X32, args.d_max, weights=w64)
         del rw["bufs"], rw["res"]
+    if args.spd:
+        import numpy as np
+        ip, ix, av = synth.grid_laplacian_spd(args.grid, args.grid, 1.0)
+        A = rbd.CsrMatrix(torch.from_numpy(ip).to(dev), torch.from_numpy(ix).to(dev), torch.from_numpy(av).to(dev))
+        log("general SPD A = I + L (5-point grid Laplacian), FP32 storage")
+        bufs = rbd.FitBuffers(m, n, args.d_max, X32.dtype, dev, spd=True)
+        for _ in range(args.warmup):
+            rbd.fit_into(bufs, X32, tol=0.0, A=A)
+        torch.cuda.synchronize()
+        from paper_1503_05947_amd import _lib
+        with _lib.Profiler(max_steps=args.d_max) as prof:
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                rbd.fit_into(bufs, X32, tol=0.0, A=A)
+            torch.cuda.synchronize()
+            secs = (time.perf_counter() - t0) / args.steps
+        rs = bufs.result()
+        gbs = m * n * 4 / (prof.avg_ms("xscan") * 1e-3) / 1e9
+        out["spd"] = {"A": f"I + L, 5-point Laplacian of the {args.grid} x {args.grid} grid (CSR, nnz {len(av)})",
+                      "value": round(rs.d / secs, 3), "unit": "greedy steps/s", "ms_per_fit": round(secs * 1e3, 3),
+                      "greedy_steps_per_fit": rs.d, "xscan_GBs": round(gbs, 1),
+                      "xscan_frac": round(gbs / PEAK_HBM_GBS, 4), "cost_vs_identity": round(secs / sec32, 3),
+                      "phases_ms_per_fit": {p: round(prof.phase_ms[p] / args.steps, 2) for p in _lib.PHASES}}
+        del bufs, A
+        torch.cuda.empty_cache()
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:

@@ -109,3 +109,47 @@ def test_parametric_field_full_size_weighted(dtype):
         x = Xj[:, jj]
         e_k = anorm((x - Y[:, :k] @ T[:k, piv[k]])[:, None])[0]
         assert abs(e_k - hist[k]) <= 1e-5 * E0, (k, e_k, hist[k])
+
+
+def test_parametric_field_full_size_spd():
+    """A = I + L (5-point Laplacian of the 1024 x 1024 grid), FP32, d_max 512 (tol 0)."""
+    import scipy.sparse as sp
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    print("[gpu] spd parametric field 1048576 x 4096 dtype=f32 d_max=512", flush=True)
+    pf = synth.parametric_field(seed=0)
+    ip, ix, av = synth.grid_laplacian_spd(1024, 1024, 1.0)
+    dev = "cuda:0"
+    A = rbd.CsrMatrix(torch.from_numpy(ip).to(dev), torch.from_numpy(ix).to(dev), torch.from_numpy(av).to(dev))
+    X = torch.empty((pf.m, pf.n), dtype=torch.float32, device=dev)
+    pf.fill_device(X)
+    res = rbd.fit(X, tol=0.0, d_max=512, A=A)
+    del X
+    torch.cuda.empty_cache()
+    assert res.d == 512 and res.stop == "dmax"
+    Ah = sp.csr_matrix((av, ix, ip), shape=(pf.m, pf.m))
+    piv = res.pivots.cpu().numpy()
+    hist = res.err_hist.cpu().numpy()
+    col_err = res.col_err.cpu().numpy()
+    T = res.T.cpu().numpy()
+    Y = res.Y.cpu().numpy()
+    E0 = hist[0]
+    assert len(set(piv.tolist())) == 512
+    g = np.random.default_rng(9)
+    steps = [0, 1, 2, 100, 511]
+    J = np.unique(np.concatenate([g.choice(pf.n, 5, replace=False), piv[steps]]))
+    Xj = synth.quantize(pf.columns(J), "f32")[1]
+    nx = np.linalg.norm(Xj, axis=0)
+    assert np.max(np.abs(Y.T @ Xj - T[:, J]) / nx) <= 1e-12
+
+    def anorm(R):
+        return np.sqrt(np.maximum(np.einsum("ij,ij->j", R, Ah @ R), 0.0))
+
+    true_err = anorm(Xj - Y @ T[:, J])
+    true_err[np.isin(J, piv)] = 0.0
+    assert np.max(np.abs(true_err - col_err[J])) <= 1e-5 * E0
+    for k in steps:
+        jj = int(np.searchsorted(J, piv[k]))
+        e_k = anorm((Xj[:, jj] - Y[:, :k] @ T[:k, piv[k]])[:, None])[0]
+        assert abs(e_k - hist[k]) <= 1e-5 * E0, (k, e_k, hist[k])
