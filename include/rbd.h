@@ -117,8 +117,8 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
 
 /*
  * rbd_fit_weighted -- Algorithm 1 with the A-norm of section 3.2 for a general
- * diagonal A = diag(weights) ("part of each data entry needs to be preserved
- * better"): the basis Y and T = Y'X are built exactly as by rbd_fit, but
+ * diagonal A = diag(weights), which weights some entries of every column
+ * more than others: the basis Y and T = Y'X are built exactly as by rbd_fit, but
  * every error of step 2.3 (hence E_0, the relative tolerance, the pivot
  * choice, col_err and err_hist) is ||x_j - Y T(:, j)||_A, eq. (3).
  *   weights  m FP64 device values, all > 0 (not checked on the device); the
@@ -134,8 +134,9 @@ int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t 
 
 /*
  * rbd_fit_spd -- Algorithm 1 with the A-norm of section 3.2 for a general
- * symmetric positive definite A ("preserve data across different entries
- * anisotropically"), A given in CSR form:
+ * symmetric positive definite A, which can couple different entries of a
+ * column (for instance an energy norm of a field on a grid), A given in CSR
+ * form:
  *   a_indptr   m + 1 int64 row offsets into a_indices / a_values
  *   a_indices  a_nnz int32 column indices in [0, m)
  *   a_values   a_nnz FP64 values
@@ -165,8 +166,8 @@ int rbd_fit_spd(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, 
 int rbd_project_workspace_size(int64_t m, int32_t d, int64_t k, rbd_dtype vt, size_t* bytes);
 
 /*
- * rbd_project -- out-of-sample compression (section 3.1, "Evaluate the
- * compression of out-of-sample data"): v_C = Y' v for each column v of V,
+ * rbd_project -- out-of-sample compression (section 3.1, the
+ * compression of out-of-sample data): v_C = Y' v for each column v of V,
  * with the A = I error of eq. (3), ||v - Y v_C||, as the error indicator.
  *
  *   Y        m x d row-major FP64 with leading dimension ldy >= d; columns are
@@ -285,7 +286,7 @@ int rbd_reconstruct_backward(const void* X, rbd_dtype xt, int64_t ldx, const voi
 /*
  * rbd_classify -- recognition of out-of-sample data in the compressed
  * coordinates: each query v (a column of V) is compressed as c = Y'v
- * (section 3.1, "Evaluate the compression of out-of-sample data") and matched
+ * (section 3.1, compression of out-of-sample data) and matched
  * to the training sample j whose coordinates T(:, j) are nearest,
  *   j* = argmin_j sum_i (c_i - T(i, j))^2,
  * the differences squared and summed in FP64 term by term in ascending i; the

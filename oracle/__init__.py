@@ -14,8 +14,8 @@ Contents
 ``rbd_brute``    Brute-force greedy for tiny inputs: every step re-derives each
                  column's projection error from a fresh QR of the chosen
                  columns (section 3.1, step 2.3 by definition).
-``rbd_project``  Out-of-sample compression v_C = Y' v (section 3.1, "Evaluate
-                 the compression of out-of-sample data") with the A = I error
+``rbd_project``  Out-of-sample compression v_C = Y' v (section 3.1, the
+                 compression of out-of-sample data) with the A = I error
                  of eq. (3) evaluated as the norm of the explicit residual.
 ``rbd_classify`` Classification of out-of-sample data in the compressed
                  coordinates (the face recognition use of section 4): each

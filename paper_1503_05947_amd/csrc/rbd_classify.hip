@@ -1,7 +1,7 @@
 // Recognition of out-of-sample data in the compressed coordinates.
 //
-// Each query v is compressed as c = Y'v (section 3.1, "Evaluate the
-// compression of out-of-sample data"), and matched to the training sample
+// Each query v is compressed as c = Y'v (section 3.1, the
+// compression of out-of-sample data), and matched to the training sample
 // whose coordinates T(:, j) are nearest in the Euclidean norm of R^d -- the
 // use of the compressed representation for face recognition in section 4.
 // The only work that depends on the entry length m is the product Y'V (an
