@@ -5,7 +5,8 @@
 // in FP64, FP32, BF16 or FP16 (widened exactly to FP64 when staged).
 //
 // Tiling: 128 x 128 output tile per workgroup (4 waves, 64 x 64 each, i.e.
-// 4 x 4 MFMA tiles of 16 x 16), k staged through LDS 16 deep.  MFMA operand
+// 4 x 4 MFMA tiles of 16 x 16), k staged through LDS 16 deep with the next
+// chunk's loads in flight while the current one is multiplied.  MFMA operand
 // layout (16x16x4, wave64): lane l supplies A(l % 16, l / 16) and
 // B(l / 16, l % 16); accumulator register r of lane l holds C(4 r + l / 16,
 // l % 16).  With `splits` > 1 the k range is divided over blockIdx.z and each
@@ -41,31 +42,47 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-    for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
-        // stage op(A)(row0 .. +128, k0 .. +16) and op(B)(k0 .. +16, col0 .. +128)
+    // the next chunk's operands are loaded into registers while the current
+    // chunk, already in LDS, is multiplied
+    constexpr int QA = (kGM * kGK) / 256, QB = (kGN * kGK) / 256;
+    double ra[QA], rb[QB];
+    auto load = [&](int64_t k0) {
 #pragma unroll
-        for (int q = 0; q < (kGM * kGK) / 256; ++q) {
+        for (int q = 0; q < QA; ++q) {
             const int e = tid + 256 * q;
             int i, k;
             if (TA) { k = e / kGM; i = e % kGM; }     // A stored K x M: rows of A are k
             else { i = e / kGK; k = e % kGK; }        // A stored M x K
             const int64_t gi = row0 + i, gk = k0 + k;
-            double v = 0.0;
-            if (gi < M && gk < ke) v = TA ? Ld<TAe>::one(A + gk * lda + gi) : Ld<TAe>::one(A + gi * lda + gk);
-            As[k][i] = v;
+            ra[q] = (gi < M && gk < ke) ? (TA ? Ld<TAe>::one(A + gk * lda + gi) : Ld<TAe>::one(A + gi * lda + gk)) : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < (kGN * kGK) / 256; ++q) {
+        for (int q = 0; q < QB; ++q) {
             const int e = tid + 256 * q;
             int j, k;
             if (TB) { j = e / kGK; k = e % kGK; }     // B stored N x K
             else { k = e / kGN; j = e % kGN; }        // B stored K x N
             const int64_t gj = col0 + j, gk = k0 + k;
-            double v = 0.0;
-            if (gj < N && gk < ke) v = TB ? Ld<TBe>::one(B + gj * ldb + gk) : Ld<TBe>::one(B + gk * ldb + gj);
-            Bs[k][j] = v;
+            rb[q] = (gj < N && gk < ke) ? (TB ? Ld<TBe>::one(B + gj * ldb + gk) : Ld<TBe>::one(B + gk * ldb + gj)) : 0.0;
+        }
+    };
+    if (kb < ke) load(kb);
+    for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
+        __syncthreads();      // the previous chunk's products are done with LDS
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + 256 * q;
+            if (TA) As[e / kGM][e % kGM] = ra[q];
+            else As[e % kGK][e / kGK] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + 256 * q;
+            if (TB) Bs[e % kGK][e / kGK] = rb[q];
+            else Bs[e / kGN][e % kGN] = rb[q];
         }
         __syncthreads();
+        if (k0 + kGK < ke) load(k0 + kGK);
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
             double af[4], bf[4];
@@ -79,7 +96,6 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-        __syncthreads();
     }
     double* out = part ? part + (int64_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
