@@ -7,9 +7,10 @@
 //
 // Per matrix b (m x n, row-major, leading dimension n) the workgroup keeps
 //   v        the working vector, in LDS (m <= kBatchMaxM)
-//   Yt       the basis transposed (D x m, one basis vector per row) in the
-//            workspace, so every Gram-Schmidt access is coalesced; Y_b is
-//            written row-major at the end
+//   Yt       the basis transposed (D x m, one basis vector per row), its
+//            first KL = ycap / m vectors in LDS and the rest in the workspace,
+//            so every Gram-Schmidt access is coalesced (or an LDS access);
+//            Y_b is written row-major at the end
 //   e2, b2   downdated and last exact squared errors (workspace)
 // and applies the same certified refresh as rbd_fit: a column whose downdated
 // error falls below 2^-20 of its last exact value is re-evaluated exactly
@@ -135,11 +136,13 @@ __device__ __forceinline__ void bsum_n(double (&v)[R], double* red) {
     __syncthreads();
 }
 
-// sum_{k<K} Yt[k*m + i] * h[k] with 8 independent loads in flight
-__device__ __forceinline__ double yt_dot(const double* __restrict__ Yt, int64_t m, int i, const double* h, int K) {
+// sum_{k0<=k<k1} Yt[k*m + i] * h[k] with 8 independent loads in flight (Yt in
+// LDS or in global memory; the caller splits the range between the two)
+__device__ __forceinline__ double yt_dot(const double* __restrict__ Yt, int64_t m, int i, const double* h, int k0,
+                                         int k1) {
     double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 8 <= K; k += 8) {
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
         double y[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) y[u] = Yt[(int64_t)(k + u) * m + i];
@@ -149,7 +152,7 @@ __device__ __forceinline__ double yt_dot(const double* __restrict__ Yt, int64_t 
             s1 = fma(y[u + 1], h[k + u + 1], s1);
         }
     }
-    for (; k < K; ++k) s0 = fma(Yt[(int64_t)k * m + i], h[k], s0);
+    for (; k < k1; ++k) s0 = fma(Yt[(int64_t)k * m + i], h[k], s0);
     return s0 + s1;
 }
 
@@ -163,11 +166,12 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
     int stride, unsigned* __restrict__ queue, double tol, int rel, int d_max, double* __restrict__ Yout,
     double* __restrict__ Tout, int64_t* __restrict__ pivots, double* __restrict__ col_err,
     double* __restrict__ err_hist, int32_t* __restrict__ d_out, int32_t* __restrict__ status,
-    double* __restrict__ wsd) {
+    double* __restrict__ wsd, int vcap, int ycap) {
     using L = Ld<Tx>;
     constexpr int NW = TPB / kWave;
     extern __shared__ double lds[];
-    double* vs = lds;                       // m
+    double* vs = lds;                       // m <= vcap
+    double* ylds = lds + vcap;              // the first KL basis vectors (KL * m <= ycap)
     __shared__ double h1[kBatchMaxD];
     __shared__ double h2[kBatchMaxD];
     __shared__ double sred[NW];
@@ -192,6 +196,9 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
         double* ceb = col_err + dsc[kDescC];
         double* Yt = wsd + dsc[kDescW];
         double* e2 = Yt + (int64_t)D * m;
+        const int KL = min(D, ycap / max(m, 1));    // basis vectors kept in LDS
+        // basis vector k (transposed layout, m contiguous values)
+        auto ycol = [&](int k) -> double* { return k < KL ? ylds + (int64_t)k * m : Yt + (int64_t)k * m; };
         double* b2 = e2 + n;
         int64_t* pvb = pivots + (int64_t)b * d_max;
         double* ehb = err_hist + (int64_t)b * (d_max + 1);
@@ -235,11 +242,12 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
             // step 2.1 + first Gram-Schmidt pass: v = x_p - Y h1, h1 = T(0:d, p)
             for (int k = tid; k < d; k += TPB) h1[k] = Tb[(int64_t)k * n + p];
             __syncthreads();
-            for (int i = tid; i < m; i += TPB) vs[i] = L::one(Xb + (int64_t)i * n + p) - yt_dot(Yt, m, i, h1, d);
+            for (int i = tid; i < m; i += TPB)
+                vs[i] = L::one(Xb + (int64_t)i * n + p) - yt_dot(ylds, m, i, h1, 0, min(d, KL)) -
+                        yt_dot(Yt, m, i, h1, min(d, KL), d);
             __syncthreads();
             // h2 = Y' v1: one wave per basis vector
-            for (int k = w; k < d; k += NW) {
-                const double* yk = Yt + (int64_t)k * m;
+            auto col_dot = [&](const double* __restrict__ yk) {
                 double s0 = 0.0, s1 = 0.0;
                 int i = lane;
                 for (; i + 3 * kWave < m; i += 4 * kWave) {
@@ -250,14 +258,17 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
                     s1 = fma(a3, vs[i + 3 * kWave], s1);
                 }
                 for (; i < m; i += kWave) s0 = fma(yk[i], vs[i], s0);
-                const double sw = wave_sum(s0 + s1);
+                return wave_sum(s0 + s1);
+            };
+            for (int k = w; k < d; k += NW) {
+                const double sw = k < KL ? col_dot(ylds + (int64_t)k * m) : col_dot(Yt + (int64_t)k * m);
                 if (lane == 0) h2[k] = sw;
             }
             __syncthreads();
             // second pass and its norm
             double acc = 0.0;
             for (int i = tid; i < m; i += TPB) {
-                const double v = vs[i] - yt_dot(Yt, m, i, h2, d);
+                const double v = vs[i] - yt_dot(ylds, m, i, h2, 0, min(d, KL)) - yt_dot(Yt, m, i, h2, min(d, KL), d);
                 vs[i] = v;
                 acc = fma(v, v, acc);
             }
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
             for (int i = tid; i < m; i += TPB) {
                 const double xi = vs[i] * inv;
                 vs[i] = xi;
-                Yt[(int64_t)d * m + i] = xi;
+                ycol(d)[i] = xi;
             }
             __syncthreads();
             // T(d, :) = xi' X, downdate, queue columns for exact evaluation
@@ -310,22 +321,26 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
                         int cols[kRG];
 #pragma unroll
                         for (int g = 0; g < kRG; ++g) cols[g] = flist[min(q0 + g, nq - 1)];
-                        int k = 0;
-                        for (; k + 4 <= d + 1; k += 4) {
-                            double y[4];
+                        auto part_sum = [&](const double* __restrict__ Yp, int k0, int k1) {
+                            int k = k0;
+                            for (; k + 4 <= k1; k += 4) {
+                                double y[4];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) y[u] = Yt[(int64_t)(k + u) * m + i];
+                                for (int u = 0; u < 4; ++u) y[u] = Yp[(int64_t)(k + u) * m + i];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u)
+                                for (int u = 0; u < 4; ++u)
 #pragma unroll
-                                for (int g = 0; g < kRG; ++g)
-                                    acc[g] = fma(y[u], Tb[(int64_t)(k + u) * n + cols[g]], acc[g]);
-                        }
-                        for (; k <= d; ++k) {
-                            const double y = Yt[(int64_t)k * m + i];
+                                    for (int g = 0; g < kRG; ++g)
+                                        acc[g] = fma(y[u], Tb[(int64_t)(k + u) * n + cols[g]], acc[g]);
+                            }
+                            for (; k < k1; ++k) {
+                                const double y = Yp[(int64_t)k * m + i];
 #pragma unroll
-                            for (int g = 0; g < kRG; ++g) acc[g] = fma(y, Tb[(int64_t)k * n + cols[g]], acc[g]);
-                        }
+                                for (int g = 0; g < kRG; ++g) acc[g] = fma(y, Tb[(int64_t)k * n + cols[g]], acc[g]);
+                            }
+                        };
+                        part_sum(ylds, 0, min(d + 1, KL));
+                        part_sum(Yt, min(d + 1, KL), d + 1);
 #pragma unroll
                         for (int g = 0; g < kRG; ++g)
                             if (q0 + g < nq) {
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
         for (int j = tid; j < n; j += TPB) ceb[j] = sqrt(e2[j]);
         for (int64_t e = tid; e < (int64_t)m * d_max; e += TPB) {
             const int i = (int)(e / d_max), k = (int)(e % d_max);
-            Yb[e] = k < d ? Yt[(int64_t)k * m + i] : 0.0;
+            Yb[e] = k < d ? (k < KL ? ylds[(int64_t)k * m + i] : Yt[(int64_t)k * m + i]) : 0.0;
         }
         for (int64_t e = (int64_t)d * n + tid; e < (int64_t)d_max * n; e += TPB) Tb[e] = 0.0;
         for (int k = d + tid; k < d_max; k += TPB) pvb[k] = -1;

@@ -48,9 +48,28 @@ hipError_t launch_batched(const Tx* X, const int64_t* desc, const int* order, in
                           hipStream_t s) {
     unsigned* queue = reinterpret_cast<unsigned*>(ws);
     double* wsd = reinterpret_cast<double*>(ws + kHeader);
+    // LDS: v (max_m doubles), then as many basis vectors as fit in this
+    // workgroup's share of the CU's LDS (grid / CUs workgroups per CU)
+    int dev = 0, per_cu = 0, per_block = 0;
+    hipFuncAttributes attr{};
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(&batched_fit_kernel<Tx, TPB>)) != hipSuccess)
+        return hipErrorInvalidValue;
+    const int wg_per_cu = std::max(1, grid / std::max(1, cu_count()));
+    const int64_t share = std::min<int64_t>(per_block, per_cu / wg_per_cu) - (int64_t)attr.sharedSizeBytes - 256;
+    const int64_t vbytes = 8 * max_m;
+    const int ycap = (int)std::max<int64_t>(0, (share - vbytes) / 8);
+    const size_t dyn = (size_t)vbytes + 8 * (size_t)ycap;
+    if ((int64_t)dyn > std::max<int64_t>(vbytes, share)) return hipErrorInvalidValue;
+    // allow dynamic LDS beyond the default per-launch limit (the request is checked at launch)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&batched_fit_kernel<Tx, TPB>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     batch_queue_reset_kernel<<<1, 64, 0, s>>>(queue);
-    batched_fit_kernel<Tx, TPB><<<grid, TPB, sizeof(double) * max_m, s>>>(
-        X, desc, order, nitems, stride, queue, tol, rel, d_max, Y, T, pivots, col_err, err_hist, d_out, status, wsd);
+    batched_fit_kernel<Tx, TPB><<<grid, TPB, dyn, s>>>(X, desc, order, nitems, stride, queue, tol, rel, d_max, Y, T,
+                                                        pivots, col_err, err_hist, d_out, status, wsd, (int)max_m,
+                                                        ycap);
     return hipGetLastError();
 }
 
