@@ -256,7 +256,7 @@ def batched_section(rbd, count, K, W, d_max=128, tol=1e-6):
     plan = rbd.BatchPlan(ms, ns, d_max, torch.float32, dev)
     Xp = torch.from_numpy(np.concatenate([A.reshape(-1) for A in mats])).to(dev)
     del mats
-    cfg = plan.autotune(Xp, tol=tol, rel=True, sample_stride=16)
+    cfg = plan.autotune(Xp, tol=tol, rel=True)
     for _ in range(W):
         plan.run(Xp, tol=tol, rel=True)
     torch.cuda.synchronize()

@@ -237,13 +237,15 @@ int rbd_fit_batched(const void* X, rbd_dtype xt, const int64_t* desc, const int3
 
 /*
  * rbd_batched_autotune -- empirical choice of rbd_batch_config: runs every
- * candidate (threads 128..1024 x 1, 2, 4 workgroups per compute unit) twice on
- * the sub-batch order[0], order[s], order[2s], ... (s = sample_stride), keeps
- * the fastest second run, and writes it to *best (and the 12 times in ms to
- * trial_ms when not NULL, threads-major; -1 for a shape that cannot be
- * launched, e.g. for lack of LDS).  Overwrites the sampled matrices'
- * outputs and WAITS for the stream.  Same arguments otherwise as
- * rbd_fit_batched.
+ * candidate (threads 128..1024 x 1, 2, 4, 8 workgroups per compute unit)
+ * twice on the sub-batch order[0], order[s], order[2s], ... (s =
+ * sample_stride), keeps the fastest second run, and writes it to *best (and
+ * the 16 times in ms to trial_ms when not NULL, threads-major; -1 for a shape
+ * that cannot be launched, e.g. for lack of LDS).  The sub-batch should give
+ * every workgroup several matrices (at least about 4 x 8 x the number of
+ * compute units), or the times measure single-matrix latency rather than
+ * throughput.  Overwrites the sampled matrices' outputs and WAITS for the
+ * stream.  Same arguments otherwise as rbd_fit_batched.
  */
 int rbd_batched_autotune(const void* X, rbd_dtype xt, const int64_t* desc, const int32_t* order, int32_t batch,
                          double tol, rbd_tol_mode mode, int32_t d_max, int32_t sample_stride,

@@ -319,20 +319,27 @@ class BatchPlan:
                 self.err_hist.data_ptr(), ints, ints + 4 * self.batch, int(self.sizes.max_m),
                 self.workspace.data_ptr(), self.workspace.numel())
 
-    def autotune(self, Xp, tol=0.0, rel=False, sample_stride=16, stream=None):
-        """Pick the workgroup shape by timing every candidate on a sub-batch (waits for the device)."""
+    def autotune(self, Xp, tol=0.0, rel=False, sample_stride=None, stream=None):
+        """Pick the workgroup shape by timing every candidate on a sub-batch (waits for the device).
+
+        The default stride keeps at least 4 matrices per workgroup at the largest
+        candidate grid (8 workgroups per compute unit), so that the trials time
+        throughput, not the latency of the largest matrix."""
         import ctypes
         torch = _torch()
+        if sample_stride is None:
+            cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+            sample_stride = max(1, self.batch // (4 * 8 * cus))
         best = _lib.BatchConfig()
-        times = (ctypes.c_double * 12)()
+        times = (ctypes.c_double * 16)()
         with torch.cuda.device(self.device):
             s = stream if stream is not None else torch.cuda.current_stream(self.device)
             rc = load().rbd_batched_autotune(*self._args(Xp, tol, rel), int(sample_stride), *self._outs(),
                                              s.cuda_stream, ctypes.byref(best), ctypes.cast(times, ctypes.c_void_p))
         _lib.check(rc, "rbd_batched_autotune")
         self.config = BatchConfig(best.threads, best.wg_per_cu)
-        self.trials = {(t, w): times[i * 3 + k] for i, t in enumerate((128, 256, 512, 1024))
-                       for k, w in enumerate((1, 2, 4))}
+        self.trials = {(t, w): times[i * 4 + k] for i, t in enumerate((128, 256, 512, 1024))
+                       for k, w in enumerate((1, 2, 4, 8))}
         return self.config
 
     def run(self, Xp, tol=0.0, rel=False, config=None, stream=None):

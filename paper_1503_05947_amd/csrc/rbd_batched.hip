@@ -208,12 +208,12 @@ int rbd_batched_autotune(const void* X, rbd_dtype xt, const int64_t* desc, const
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return RBD_EDEVICE;
     const int threads[4] = {128, 256, 512, 1024};
-    const int wgs[3] = {1, 2, 4};
+    const int wgs[4] = {1, 2, 4, 8};
     float best_ms = 0.f;
     int t = 0, rc = RBD_OK;
     bool found = false;
     for (int ti = 0; ti < 4 && rc == RBD_OK; ++ti)
-        for (int wi = 0; wi < 3 && rc == RBD_OK; ++wi, ++t) {
+        for (int wi = 0; wi < 4 && rc == RBD_OK; ++wi, ++t) {
             rbd_batch_config c{threads[ti], wgs[wi]};
             float ms = 0.f;
             bool ok = true;
