@@ -665,8 +665,8 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
                                                                   nullptr, cc, P.rc_rows, P.rc_S, nullptr, 0, nullptr,
                                                                   rbuf, Q.cq);
                 RBD_LAUNCH_CHECK();
-                csr_quad_kernel<<<dim3((unsigned)cdiv(cc, 64), (unsigned)Q.q_S), 64, 0, s>>>(rbuf, Q.cq, P.m, cc, A,
-                                                                                          Q.q_rows, qpart, P.n, c0);
+                csr_quad_kernel<<<dim3((unsigned)cdiv(cc, 64), (unsigned)Q.q_S), 64 * kQuadGroups, 0, s>>>(
+                    rbuf, Q.cq, P.m, cc, A, Q.q_rows, qpart, P.n, c0);
                 RBD_LAUNCH_CHECK();
             }
         }

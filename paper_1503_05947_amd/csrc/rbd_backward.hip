@@ -45,6 +45,33 @@ __global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int
     }
 }
 
+// The same inverse for d <= kRinvLds in one workgroup: Rinv is held in LDS and
+// its rows are formed bottom-up, row i for every column j > i at once
+// (thread j; the sum over k runs in the same ascending order as rinv_kernel,
+// so both give identical results); row i of R is staged in LDS first.
+constexpr int kRinvLds = 128;
+__global__ __launch_bounds__(kRinvLds) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
+                                                            const int64_t* __restrict__ piv, int d,
+                                                            double* __restrict__ Rinv) {
+    extern __shared__ double xs[];           // d x d
+    __shared__ double rrow[kRinvLds];
+    const int j = threadIdx.x;
+    for (int i = 0; i < d; ++i)
+        if (j < d) xs[i * d + j] = (i == j) ? 1.0 / T[(int64_t)j * ldt + piv[j]] : 0.0;
+    for (int i = d - 2; i >= 0; --i) {
+        __syncthreads();                      // row i + 1 of Rinv is complete
+        if (j < d) rrow[j] = T[(int64_t)i * ldt + piv[j]];
+        __syncthreads();
+        if (j > i && j < d) {
+            double sum = 0.0;
+            for (int k = i + 1; k <= j; ++k) sum = fma(rrow[k], xs[k * d + j], sum);
+            xs[i * d + j] = -sum / rrow[i];
+        }
+    }
+    __syncthreads();
+    for (int e = j; e < d * d; e += blockDim.x) Rinv[e] = xs[e];
+}
+
 // S = tril(M) + tril(M, -1)'
 __global__ void copyltu_kernel(const double* __restrict__ Mm, int d, double* __restrict__ S) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,7 +139,14 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     ok(hipGetLastError());
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
     // Abar = Ybar R^{-T};  dX(:, P) += Abar
-    rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, Rinv);
+    if (d <= kRinvLds) {
+        const size_t lds = sizeof(double) * (size_t)d * d;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        rinv_lds_kernel<<<1, kRinvLds, lds, s>>>(T, ldt, piv, d, Rinv);
+    } else {
+        rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, Rinv);
+    }
     ok(hipGetLastError());
     ok(gemm<false, true, double, double>(m, d, d, 1.0, Ybar, d, Rinv, d, 0.0, Abar, d, nullptr, 0, s));
     scatter_add_cols_kernel<<<(unsigned)std::min<int64_t>(4096, cd(m * d, 256)), 256, 0, s>>>(Abar, m, d, piv, dX,

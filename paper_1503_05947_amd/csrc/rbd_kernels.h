@@ -1075,14 +1075,19 @@ __global__ void set_wxx_kernel(State* __restrict__ st, const double* __restrict_
 
 // csr_quad: part[slab * ldp + c0 + jj] = sum_{i in slab} r_i,jj (A r_jj)_i for
 // the residual columns jj < cnt held in R (m x cnt, leading dimension ldr).
-__global__ __launch_bounds__(64) void csr_quad_kernel(const double* __restrict__ R, int64_t ldr, int64_t m, int cnt,
-                                                       Csr A, int rows_per_slab, double* __restrict__ part,
-                                                       int64_t ldp, int c0) {
-    const int jj = blockIdx.x * blockDim.x + threadIdx.x;
+// Block: 64 columns x kQuadGroups row groups (rows r0 + g, r0 + g + groups,
+// ...), combined in LDS in a fixed order.
+constexpr int kQuadGroups = 4;
+__global__ __launch_bounds__(64 * kQuadGroups) void csr_quad_kernel(const double* __restrict__ R, int64_t ldr, int64_t m,
+                                                                    int cnt, Csr A, int rows_per_slab,
+                                                                    double* __restrict__ part, int64_t ldp, int c0) {
+    __shared__ double red[kQuadGroups][64];
+    const int lane = threadIdx.x % 64, grp = threadIdx.x / 64;
+    const int jj = blockIdx.x * 64 + lane;
     const int jc = jj < cnt ? jj : cnt - 1;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab, r1 = min(m, r0 + (int64_t)rows_per_slab);
     double acc = 0.0;
-    for (int64_t i = r0; i < r1; ++i) {
+    for (int64_t i = r0 + grp; i < r1; i += kQuadGroups) {
         int64_t e0, e1;
         csr_row(A, i, e0, e1);
         double y = 0.0;
@@ -1092,7 +1097,13 @@ __global__ __launch_bounds__(64) void csr_quad_kernel(const double* __restrict__
         }
         acc = fma(R[i * ldr + jc], y, acc);
     }
-    if (jj < cnt) part[(int64_t)blockIdx.y * ldp + c0 + jj] = acc;
+    red[grp][lane] = acc;
+    __syncthreads();
+    if (grp == 0 && jj < cnt) {
+        double sum = red[0][lane];
+        for (int g = 1; g < kQuadGroups; ++g) sum += red[g][lane];
+        part[(int64_t)blockIdx.y * ldp + c0 + jj] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
