@@ -69,11 +69,29 @@ def parse():
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xscan_parametric_1048576x4096_traffic.json")
 
 
+# The source text that decides the X-scan's memory traffic: the kernel, the
+# storage loaders, the scan's part of the launch plan, and its launcher.
+XSCAN_SOURCES = (
+    ("rbd_kernels.h", "// X-scan: per row slab", "// update: finish the column sums"),
+    ("rbd_device.h", "template <typename Tx> struct Ld;", "// reductions"),
+    ("rbd_api.hip", "bool make_fit_plan(", "P->up_ncb"),
+    ("rbd_api.hip", "void launch_xscan(", "template <"),
+)
+
+
 def kernel_sources_sha256():
+    """Hash of the X-scan's source text; None when a marker is missing."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1503_05947_amd", "csrc")
-    blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("rbd_device.h", "rbd_kernels.h", "rbd_api.hip"))
-    return hashlib.sha256(blob).hexdigest()
+    h = hashlib.sha256()
+    for fname, start, end in XSCAN_SOURCES:
+        text = open(os.path.join(csrc, fname)).read()
+        i = text.find(start)
+        j = text.find(end, i + len(start)) if i >= 0 else -1
+        if i < 0 or j < 0:
+            return None
+        h.update(text[i:j].encode())
+    return h.hexdigest()
 
 
 def measured_traffic(key, m, n):
@@ -83,7 +101,8 @@ def measured_traffic(key, m, n):
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != kernel_sources_sha256() or (m, n) != (1 << 20, 4096):
+    sha = kernel_sources_sha256()
+    if sha is None or rec.get("source_sha256") != sha or (m, n) != (1 << 20, 4096):
         return None
     k = rec.get("kernels", {}).get(key)
     return None if k is None else round(k["traffic_bytes"])
