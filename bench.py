@@ -410,6 +410,33 @@ def classify_section(rbd, K, W, k=262144, d_max=40, cpu=True):
     return out
 
 
+def bump_field_section(rbd, K, W):
+    """The 2048 x 2048 bump field (FP32), relative tol 1e-4 with d_max 256, and the
+    same field in fixed-step mode (tol 0, all 256 steps): cache-resident, so the
+    step time is launch and dependency latency, not HBM bandwidth."""
+    import torch
+
+    import synth
+    wl = synth.bump_field(0)
+    X = torch.from_numpy(synth.quantize(wl.X, "f32")[0]).to("cuda:0")
+    out = {"workload": "bump_field 2048x2048 (50 Gaussian bumps + 1e-4 noise), FP32, d_max 256"}
+    for name, tol, rel in (("rel_tol_1e-4", wl.tol, True), ("fixed_256_steps", 0.0, False)):
+        bufs = rbd.FitBuffers(2048, 2048, wl.d_max, X.dtype, X.device)
+        for _ in range(max(W, 1)):
+            rbd.fit_into(bufs, X, tol=tol, rel=rel)
+        torch.cuda.synchronize()
+        reps = max(K, 1) * 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rbd.fit_into(bufs, X, tol=tol, rel=rel)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        d = bufs.result().d
+        out[name] = {"greedy_steps": d, "ms_per_fit": round(sec * 1e3, 3), "greedy_steps_per_s": round(d / sec, 1),
+                     "us_per_step": round(sec / max(d, 1) * 1e6, 2)}
+    return out
+
+
 def batched_cpu_baseline(count=4096, sample=24, d_max=128, tol=1e-6):
     import numpy as np
     import oracle
@@ -577,6 +604,8 @@ def main():
                       "phases_ms_per_fit": {p: round(prof.phase_ms[p] / args.steps, 2) for p in _lib.PHASES}}
         del bufs, A
         torch.cuda.empty_cache()
+    log("bump field 2048 x 2048 (FP32)")
+    out["bump_field_2048"] = bump_field_section(rbd, args.steps, args.warmup)
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:
