@@ -434,6 +434,18 @@ def bump_field_section(rbd, K, W):
         d = bufs.result().d
         out[name] = {"greedy_steps": d, "ms_per_fit": round(sec * 1e3, 3), "greedy_steps_per_s": round(d / sec, 1),
                      "us_per_step": round(sec / max(d, 1) * 1e6, 2)}
+        # the same fit as one captured graph (all steps recorded once, replayed)
+        g = rbd.FitGraph(bufs, X, tol=tol, rel=rel)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.replay()
+        torch.cuda.synchronize()
+        gsec = (time.perf_counter() - t0) / reps
+        g.close()
+        out[name]["graph_ms_per_fit"] = round(gsec * 1e3, 3)
+        out[name]["graph_greedy_steps_per_s"] = round(d / gsec, 1)
     return out
 
 

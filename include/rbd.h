@@ -133,6 +133,28 @@ int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t 
                      void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Captured fits.  rbd_fit_graph_create records the launch sequence of one
+ * rbd_fit (weights == NULL) or rbd_fit_weighted call -- all D greedy steps,
+ * each kernel of a step returning at once after the device-side stop -- into
+ * a HIP graph, without running it; rbd_fit_graph_launch replays it on any
+ * stream.  Every pointer argument is baked into the graph: a replay fits
+ * whatever X (and weights) then hold, into the same outputs and workspace,
+ * which must stay allocated until rbd_fit_graph_destroy.  `stream` must not
+ * be the null stream (capture needs a created stream); nothing runs on it
+ * during creation.  Replays on one workspace must not overlap.  Arguments
+ * and errors otherwise as for rbd_fit / rbd_fit_weighted; creation can also
+ * fail with RBD_EDEVICE if capture is not possible.
+ */
+typedef struct rbd_fit_graph_s* rbd_fit_graph;
+int rbd_fit_graph_create(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const double* weights,
+                         double tol, rbd_tol_mode mode, int32_t d_max, int64_t start,
+                         double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                         int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                         void* workspace, size_t workspace_bytes, void* stream, rbd_fit_graph* out);
+int rbd_fit_graph_launch(rbd_fit_graph graph, void* stream);
+int rbd_fit_graph_destroy(rbd_fit_graph graph);
+
+/*
  * rbd_fit_spd -- Algorithm 1 with the A-norm of section 3.2 for a general
  * symmetric positive definite A, which can couple different entries of a
  * column (for instance an energy norm of a field on a grid), A given in CSR

@@ -158,6 +158,61 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
     _lib.check(rc, "rbd_fit")
 
 
+class FitGraph:
+    """A captured fit (rbd_fit_graph_create): all D greedy steps recorded once as a
+    HIP graph; ``replay`` refits whatever X (and weights) hold, into ``bufs``, with a
+    single graph launch.  X, weights and bufs must stay alive and keep their storage."""
+
+    def __init__(self, bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: int = -1, weights=None):
+        import ctypes
+        torch = _torch()
+        _check_matrix(X, "X")
+        if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
+            raise ValueError("X does not match the buffers' shape/dtype")
+        if weights is not None and (weights.dtype != torch.float64 or weights.dim() != 1
+                                    or weights.numel() != bufs.m or weights.device != X.device
+                                    or not weights.is_contiguous()):
+            raise ValueError("weights must be a contiguous float64 vector of m values on X's device")
+        self._keep = (bufs, X, weights)
+        self.bufs = bufs
+        self.device = X.device
+        lib = load()
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(X.device):
+            cap = torch.cuda.Stream(device=X.device)      # capture needs a created stream
+            torch.cuda.current_stream(X.device).synchronize()
+            ints = bufs.ints.data_ptr()
+            rc = lib.rbd_fit_graph_create(
+                X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0),
+                weights.data_ptr() if weights is not None else None, float(tol),
+                _lib.RBD_TOL_REL if rel else _lib.RBD_TOL_ABS, bufs.d_max, int(start), bufs.Y.data_ptr(),
+                bufs.T.data_ptr(), bufs.pivots.data_ptr(), bufs.col_err.data_ptr(), bufs.err_hist.data_ptr(),
+                ints, ints + 4, ints + 8, bufs.workspace.data_ptr(), bufs.workspace.numel(), cap.cuda_stream,
+                ctypes.byref(handle))
+        _lib.check(rc, "rbd_fit_graph_create")
+        self._h = handle
+
+    def replay(self, stream=None) -> None:
+        """Enqueue one replay on ``stream`` (default: torch's current stream)."""
+        torch = _torch()
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        with torch.cuda.device(self.device):
+            s = stream if stream is not None else torch.cuda.current_stream(self.device)
+            _lib.check(load().rbd_fit_graph_launch(self._h, s.cuda_stream), "rbd_fit_graph_launch")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            load().rbd_fit_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1, stream=None,
         weights=None, A: "CsrMatrix | None" = None) -> FitResult:
     """Algorithm 1 on a device matrix X (m x n, f32/bf16/f16/f64 storage).

@@ -26,6 +26,11 @@ SIGNATURES = {
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_fit_weighted": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32, _i64,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbd_fit_graph_create": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32,
+                                            _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp,
+                                            ctypes.POINTER(_vp)]),
+    "rbd_fit_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "rbd_fit_graph_destroy": (ctypes.c_int, [_vp]),
     "rbd_fit_spd_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_fit_spd": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _dp, ctypes.c_int, _i32,
                                    _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "../../include/rbd.h"
@@ -801,6 +802,53 @@ int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t 
     if (!weights) return RBD_EINVAL;
     return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
                      stop_reason, workspace, workspace_bytes, stream, weights);
+}
+
+struct rbd_fit_graph_s {
+    hipGraphExec_t exec;
+};
+
+int rbd_fit_graph_create(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const double* weights,
+                         double tol, rbd_tol_mode mode, int32_t d_max, int64_t start, double* Y, double* T,
+                         int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
+                         int32_t* stop_reason, void* workspace, size_t workspace_bytes, void* stream,
+                         rbd_fit_graph* out) {
+    if (!out || !stream) return RBD_EINVAL;
+    *out = nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return RBD_EDEVICE;
+    const int rc = fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out,
+                             status, stop_reason, workspace, workspace_bytes, stream, weights);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != RBD_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rc != RBD_OK ? rc : RBD_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess || !exec) return RBD_EDEVICE;
+    rbd_fit_graph g = new (std::nothrow) rbd_fit_graph_s{exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return RBD_EDEVICE;
+    }
+    *out = g;
+    return RBD_OK;
+}
+
+int rbd_fit_graph_launch(rbd_fit_graph graph, void* stream) {
+    if (!graph) return RBD_EINVAL;
+    return hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? RBD_OK : RBD_EDEVICE;
+}
+
+int rbd_fit_graph_destroy(rbd_fit_graph graph) {
+    if (!graph) return RBD_OK;
+    const hipError_t e = hipGraphExecDestroy(graph->exec);
+    delete graph;
+    return e == hipSuccess ? RBD_OK : RBD_EDEVICE;
 }
 
 int rbd_fit_spd_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes) {

@@ -164,3 +164,14 @@ def test_weighted_fit_rejects_missing_weights(lib):
     rc = lib.rbd_fit_weighted(fake, 0, 10, 10, 9, fake, 0.0, 0, 5, -1, fake, fake, fake, fake, fake, fake, fake,
                               None, ctypes.c_void_p(1 << 20), 1 << 30, None)
     assert rc == _lib.RBD_EINVAL      # ldx < n
+
+
+def test_fit_graph_rejects_the_null_stream(lib):
+    from paper_1503_05947_amd import _lib
+    fake = ctypes.c_void_p(4096)
+    h = ctypes.c_void_p()
+    rc = lib.rbd_fit_graph_create(fake, 0, 16, 8, 8, None, 0.0, 0, 4, -1, fake, fake, fake, fake, fake, fake, fake,
+                                  None, ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h))
+    assert rc == _lib.RBD_EINVAL
+    assert lib.rbd_fit_graph_launch(None, None) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_graph_destroy(None) == _lib.RBD_OK
