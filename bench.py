@@ -470,7 +470,7 @@ def batched_cpu_baseline(count=4096, sample=24, d_max=128, tol=1e-6):
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle on a bounded sample of the same workload
 # ---------------------------------------------------------------------------
-def cpu_baseline(full_m, grid_sample=256, n=4096, steps=8):
+def cpu_baseline(full_m, grid_sample=256, n=4096, steps=24):
     import numpy as np
     import oracle
     import synth
