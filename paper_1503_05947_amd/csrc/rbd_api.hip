@@ -2,10 +2,12 @@
 // launch plans and the C ABI declared in include/rbd.h.
 //
 // rbd_fit enqueues the whole greedy loop on the caller's stream without ever
-// waiting for the device: for step s = 0 .. D-1 it launches the six kernels of
+// waiting for the device: for step s = 0 .. D-1 it launches the kernels of
 // one step with d = s (the device keeps the real d, and every kernel returns
 // at once after the stop flag is set).  The host therefore knows an upper
 // bound of d for each launch and sizes register tiles (KC) from it.
+// rbd_fit_spd is the exception: it reads the loop state once per step to size
+// its exact refreshes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,21 +1,27 @@
 // Kernels of the greedy loop of Reduced Basis Decomposition (Algorithm 1,
-// section 3.1) with A = I (eq. (3)).  One greedy step is a fixed sequence of
-// stream-ordered kernels; every kernel reads the device-side stop flag first,
-// so steps past the end of the loop cost one empty launch each and the host
-// never waits.
+// section 3.1) and of its A-norm variants (section 3.2, eq. (3)).  One greedy
+// step is a fixed sequence of stream-ordered kernels; every kernel reads the
+// device-side stop flag first, so steps past the end of the loop cost one
+// empty launch each and the host never waits.
 //
-//   cgs1    v1 = x_p - Y h1 with h1 = T(0:d, p)   (first Gram-Schmidt pass;
-//           h1 = Y' x_p is already a column of T), fused with per-block
-//           partial sums of h2 = Y' v1
-//   reduce  h2 = fixed-order sum of the partials (two small launches)
-//   cgs2    v2 = v1 - Y h2 (second pass) and per-block partial ||v2||^2
-//   nu      nu = ||v2||, step 2.2's break test
-//   xscan   xi = v2 / nu written to Y(:, d); partial xi' X per row slab
-//   reduce  combine slab partials into slab-group partials
-//   update  T(d, :); e_j^2 -= T(d, j)^2; queue columns whose downdated error
-//           fell below kappa * (last exact value); lowest-index argmax
-//   resid   exact ||x_j - Y T(:, j)||^2 for the queued columns (FP64 GEMM)
+// A = I (lagged reorthogonalisation: one pass over Y per step):
+//   gather_col    x_p into a contiguous FP64 vector
+//   cgs1_lag      writes the previous step's basis column, then
+//                 v1 = x_p - Y h1 with h1 = T(0:d, p) (h1 = Y' x_p is already a
+//                 column of T), with per-block partials of h2 = Y' v1, ||v1||^2
+//   reduce        h2 and ||v1||^2 = fixed-order sums (two small launches)
+//   nu_lag        nu^2 = ||v1||^2 - ||h2||^2, step 2.2's break test
+//   tcorr         correction rows -h2' T(0:d, :) / nu
+//   xscan         partial (v1 / nu)' X per row slab
+//   reduce        slab partials (and correction rows) into group partials
+//   update        T(d, :); e_j^2 -= T(d, j)^2; queue columns for an exact
+//                 refresh; lowest-index argmax
+//   ycol          the deferred basis column, when a refresh needs it
+//   resid_mfma    exact ||x_j - Y T(:, j)||^2 of queued columns (FP64 MFMA)
 //   resid_finish  store the exact values, argmax, stop test of step 2.4
+// Diagonal and general SPD A keep the explicit second pass (cgs1, cgs2) and add
+// g = (I - YY')(A xi) (gvec; spmv and ytu for a sparse A), the two-vector
+// X-scan and the weighted downdate (update<kStepW>).
 //
 // Wide kernels (thousands of workgroups) never synchronise across the grid:
 // a device-scope release fence per workgroup writes back the XCD's L2 and
