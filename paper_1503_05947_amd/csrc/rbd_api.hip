@@ -53,7 +53,7 @@ struct FitPlan {
     int ntickets = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
-    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_hw,
+    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_M, o_mh, o_hw,
         o_part,
         o_l2, o_rpart, total;
 };
@@ -126,12 +126,14 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_nu2 = take(8);
     P->o_g = take(8 * m);
     P->o_xp = take(8 * m);
+    P->o_M = take(8 * (size_t)std::max(P->D, 1) * std::max(P->D, 1));    // Y'WY (diagonal A)
+    P->o_mh = take(8 * ((size_t)RBD_MAX_D + 1));
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
     // scan partials (two rows of n per slab with a diagonal A-norm); Gram-Schmidt partials
     // (the lagged path adds up to ceil(D / kTcorr) correction rows after the scan's slabs)
     const size_t kp_max = (size_t)cdiv(std::max(P->D, 1), kTcorr);
     const size_t part_elems = std::max<size_t>(std::max<size_t>((size_t)P->sc_S * 2 * n, ((size_t)P->sc_S + kp_max) * n),
-                                               (size_t)P->cg_S * (std::max(P->D, 1) + 2));
+                                               (size_t)P->cg_S * 2 * (std::max(P->D, 1) + 1));
     P->o_part = take(8 * part_elems);
     const size_t l2_elems =
         std::max<size_t>(((size_t)P->up_SG + kp_max + 1) * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
@@ -243,6 +245,20 @@ void launch_cgs1(const FitPlan& P, const double* xp, const double* Y, const doub
 }
 
 template <int KC>
+void launch_cgs1w(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
+                  const double* w, double* v1, double* part, hipStream_t s) {
+    cgs1w_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, w, v1,
+                                                                 part, std::max(P.D, 1));
+}
+
+template <int KC>
+void launch_gvec2(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
+                  const double* hw, const double* w, double* v2, double* g, hipStream_t s) {
+    gvec2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, hw, w, v2,
+                                                                 g);
+}
+
+template <int KC>
 void launch_cgs1_lag(const FitPlan& P, const double* xp, double* Y, const double* T, State* st, int d,
                      const double* v1p, const double* h2p, double* v1, double* part, hipStream_t s) {
     cgs1_lag_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows,
@@ -276,19 +292,14 @@ void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d,
 
 template <int KC>
 void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
-                 double* v2, double* part, const double* w, hipStream_t s) {
-    if (w)
-        cgs2_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
-                                                                          v2, part, w, std::max(P.D, 1));
-    else
-        cgs2_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
-                                                                           v2, part, nullptr, std::max(P.D, 1));
+                 double* v2, double* part, hipStream_t s) {
+    cgs2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part);
 }
 
 template <int KC>
-void launch_gvec(const FitPlan& P, const double* Y, const State* st, int d, const double* v2, const double* w,
-                 const double* hw, double* g, hipStream_t s) {
-    gvec_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v2, w, hw, g);
+void launch_gvec(const FitPlan& P, const double* Y, const State* st, int d, const double* av, const double* hw,
+                 double* g, hipStream_t s) {
+    gvec_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, av, hw, g);
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
@@ -321,6 +332,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     double* g = reinterpret_cast<double*>(ws + P.o_g);
     double* hw = reinterpret_cast<double*>(ws + P.o_hw);
     double* xp = reinterpret_cast<double*>(ws + P.o_xp);
+    double* Mw = reinterpret_cast<double*>(ws + P.o_M);
+    double* mh = reinterpret_cast<double*>(ws + P.o_mh);
     const bool W = (w != nullptr);
     const int64_t nw = W ? 2 * P.n : P.n;     // scan partial row length
 
@@ -410,66 +423,52 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_RESID_FINISH, s);
         prof_step(s);
     }
-    // diagonal A: explicit second pass (it also forms the A-weighted sums)
+    // diagonal A: two passes over Y per step (M = Y'WY kept up to date)
+    double* const avec = h2 + RBD_MAX_D + 1;     // a = Y'(w . v1) and sum w v1^2
+    const int64_t ldp = std::max(P.D, 1);
     for (int d = 0; W && d < P.D; ++d) {
+        const int kc = kc_for(d);
         prof_begin(RBD_PHASE_CGS1, s);
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         RBD_LAUNCH_CHECK();
-        switch (kc_for(d)) {
-            case 1: launch_cgs1<1>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 2: launch_cgs1<2>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 4: launch_cgs1<4>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 8: launch_cgs1<8>(P, xp, Y, T, st, d, v1, part, s); break;
-            default: launch_cgs1<16>(P, xp, Y, T, st, d, v1, part, s); break;
+        switch (kc) {
+            case 1: launch_cgs1w<1>(P, xp, Y, T, st, d, w, v1, part, s); break;
+            case 2: launch_cgs1w<2>(P, xp, Y, T, st, d, w, v1, part, s); break;
+            case 4: launch_cgs1w<4>(P, xp, Y, T, st, d, w, v1, part, s); break;
+            case 8: launch_cgs1w<8>(P, xp, Y, T, st, d, w, v1, part, s); break;
+            default: launch_cgs1w<16>(P, xp, Y, T, st, d, w, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
-        if (d > 0) {
-            launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, h2, 0, s);
-            RBD_LAUNCH_CHECK();
-        }
+        launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, h2, 0, s);
+        RBD_LAUNCH_CHECK();
+        launch_sum_rows(st, part + (int64_t)P.cg_S * ldp, ldp, P.cg_S, P.cg_group, d + 1, l2, avec, 0, s);
+        RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
-        switch (kc_for(d)) {
-            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, w, s); break;
-            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, w, s); break;
-            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, w, s); break;
-            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, w, s); break;
-            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, w, s); break;
-        }
-        RBD_LAUNCH_CHECK();
-        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S, W ? 1 : 0);
-        RBD_LAUNCH_CHECK();
-        if (W) {
-            // g = P_d(A xi): hw = Y'(w . v2) from cgs2's partials, then g
-            if (d > 0) {
-                launch_sum_rows(st, part + 2 * (int64_t)P.cg_S, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, hw, 0,
-                                s);
-                RBD_LAUNCH_CHECK();
-            }
-            switch (kc_for(d)) {
-                case 1: launch_gvec<1>(P, Y, st, d, v2, w, hw, g, s); break;
-                case 2: launch_gvec<2>(P, Y, st, d, v2, w, hw, g, s); break;
-                case 4: launch_gvec<4>(P, Y, st, d, v2, w, hw, g, s); break;
-                case 8: launch_gvec<8>(P, Y, st, d, v2, w, hw, g, s); break;
-                default: launch_gvec<16>(P, Y, st, d, v2, w, hw, g, s); break;
-            }
+        if (d > 0) {
+            mv_kernel<<<(unsigned)cdiv(d, 256), 256, 0, s>>>(st, Mw, ldp, d, h2, mh);
             RBD_LAUNCH_CHECK();
         }
+        nuw_kernel<<<1, 256, 0, s>>>(st, h2, avec, mh, d, hw, Mw, ldp);
+        RBD_LAUNCH_CHECK();
+        switch (kc) {
+            case 1: launch_gvec2<1>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+            case 2: launch_gvec2<2>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+            case 4: launch_gvec2<4>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+            case 8: launch_gvec2<8>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+            default: launch_gvec2<16>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+        }
+        RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
-        if (W) launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s, g);
-        else launch_xscan<Tx, kScanDot>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s);
+        launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, -1, part, vec_ok, nt, s, g);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_XSCAN, s);
         prof_begin(RBD_PHASE_UPDATE, s);
         reduce_rows_kernel<<<red_grid_step, 256, 0, s>>>(st, part, nw, P.sc_S, up_per, nw, l2, nw);
         RBD_LAUNCH_CHECK();
-        if (W)
-            update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n,
-                                                           flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
-        else
-            update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n,
-                                                          flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+        update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flist,
+                                                       bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
@@ -609,14 +608,14 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
         switch (kc) {
-            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
-            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
-            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
-            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
-            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, nullptr, s); break;
+            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, s); break;
+            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, s); break;
+            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, s); break;
         }
         RBD_LAUNCH_CHECK();
-        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S, 0);
+        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S);
         RBD_LAUNCH_CHECK();
         // u = A v2; hw = Y'u and v2'u; g = P_d(A xi); ||xi||_A^2
         spmv_kernel<<<(unsigned)std::min<int64_t>(16384, cdiv(P.m, 256)), 256, 0, s>>>(st, A, P.m, v2, u);
@@ -634,11 +633,11 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         set_wxx_kernel<<<1, 64, 0, s>>>(st, hw, d);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_gvec<1>(P, Y, st, d, u, nullptr, hw, g, s); break;
-            case 2: launch_gvec<2>(P, Y, st, d, u, nullptr, hw, g, s); break;
-            case 4: launch_gvec<4>(P, Y, st, d, u, nullptr, hw, g, s); break;
-            case 8: launch_gvec<8>(P, Y, st, d, u, nullptr, hw, g, s); break;
-            default: launch_gvec<16>(P, Y, st, d, u, nullptr, hw, g, s); break;
+            case 1: launch_gvec<1>(P, Y, st, d, u, hw, g, s); break;
+            case 2: launch_gvec<2>(P, Y, st, d, u, hw, g, s); break;
+            case 4: launch_gvec<4>(P, Y, st, d, u, hw, g, s); break;
+            case 8: launch_gvec<8>(P, Y, st, d, u, hw, g, s); break;
+            default: launch_gvec<16>(P, Y, st, d, u, hw, g, s); break;
         }
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);

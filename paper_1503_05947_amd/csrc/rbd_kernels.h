@@ -395,43 +395,253 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
 }
 
 // ---------------------------------------------------------------------------
-// cgs2: v2 = v1 - Y(:, 0:d) h2, nu = ||v2||, and step 2.2's break test.
+// Diagonal A = diag(w) with two passes over Y per step.  With M = Y'WY kept
+// up to date (one new row and column per step), the second Gram-Schmidt pass
+// and g = (I - YY')(W xi) need no pass of their own:
+//   a  = Y'(w . v1),  hw = Y'(W xi) = (a - M h2) / nu,
+//   ||xi||_A^2 = (sum w v1^2 - 2 h2'a + h2'M h2) / nu^2,  nu^2 = ||v1||^2 - ||h2||^2,
+// and one pass forms v2 = v1 - Y h2, xi = v2 / nu (written to Y(:, d)) and
+// g = w . xi - Y hw.  h2 is at rounding level after the first pass, so the
+// corrections through M are tiny and M's own rounding does not matter.
 // ---------------------------------------------------------------------------
-template <int KC, int RU, bool W>
-__global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
-                                                    State* __restrict__ st, int d, int rows_per_blk,
-                                                    const double* __restrict__ v1, const double* __restrict__ h2,
-                                                    double* __restrict__ v2, double* __restrict__ part,
-                                                    const double* __restrict__ w, int64_t ldp) {
-    // part[blk] = sum ||v2||^2; with W also part[S + blk] = sum w v2^2 and
-    // part[2S + blk*ldp + k] = sum_i Y[i,k] w_i v2_i   (S = gridDim.x)
+
+// cgs1w: v1 = x_p - Y h1 as in cgs1, with per-block partials of h2 = Y'v1
+// and ||v1||^2 (part[blk * ldp + k], k <= d) and of a = Y'(w . v1) and
+// sum w v1^2 (the same layout, gridDim.x * ldp further on).
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ xp, int64_t m,
+                                                     const double* __restrict__ Y, int64_t ldy,
+                                                     const double* __restrict__ T, int64_t ldt,
+                                                     State* __restrict__ st, int d, int rows_per_blk,
+                                                     const double* __restrict__ w, double* __restrict__ v1,
+                                                     double* __restrict__ part, int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
-    __shared__ double accs[W ? KW : 1];
+    __shared__ double accs[KW];
+    __shared__ double accw[KW];
     __shared__ double sred[4];
+    const int p = st->p;
     for (int k = threadIdx.x; k < KW; k += blockDim.x) {
-        hs[k] = (k < d) ? h2[k] : 0.0;
-        if (W) accs[k] = 0.0;
+        hs[k] = (k < d) ? T[(int64_t)k * ldt + p] : 0.0;
+        accs[k] = 0.0;
+        accw[k] = 0.0;
     }
     __syncthreads();
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
-    double nacc = 0.0, wacc = 0.0;
-    double hacc[W ? KC : 1];
+    double acc[KC], acw[KC];
 #pragma unroll
-    for (int c = 0; c < (W ? KC : 1); ++c) hacc[c] = 0.0;
+    for (int c = 0; c < KC; ++c) acc[c] = acw[c] = 0.0;
+    double nacc = 0.0, wacc = 0.0;
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+        double xv[RU], wr[RU], dot[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+            xv[u] = ok ? xp[r] : 0.0;
+            wr[u] = ok ? w[r] : 0.0;
+            dot[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
+        wave_sum_n<RU>(dot);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const double v = xv[u] - dot[u];   // rows past the end have y = 0, x = 0, w = 0
+            const double wvv = wr[u] * v;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                acc[c] = fma(y[u][c], v, acc[c]);
+                acw[c] = fma(y[u][c], wvv, acw[c]);
+            }
+            if (lane == u && rb + u < r1) {
+                v1[rb + u] = v;
+                nacc = fma(v, v, nacc);
+                wacc = fma(wvv, v, wacc);
+            }
+        }
+    }
+    const double nn = block_sum(nacc, sred);
+    const double ww = block_sum(wacc, sred);
+    double* p0 = part + (int64_t)blockIdx.x * ldp;
+    double* p1 = part + (int64_t)gridDim.x * ldp + (int64_t)blockIdx.x * ldp;
+    if (threadIdx.x == 0) {
+        p0[d] = nn;
+        p1[d] = ww;
+    }
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (wv == q) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                accs[lane + kWave * c] += acc[c];
+                accw[lane + kWave * c] += acw[c];
+            }
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        p0[k] = accs[k];
+        p1[k] = accw[k];
+    }
+}
+
+// mv: Mh = M(0:d, 0:d) h2 (M symmetric, so column reads: coalesced)
+__global__ __launch_bounds__(256) void mv_kernel(const State* __restrict__ st, const double* __restrict__ M,
+                                                  int64_t ldm, int d, const double* __restrict__ h2,
+                                                  double* __restrict__ Mh) {
+    if (st->stop) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d) return;
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) s = fma(M[(int64_t)j * ldm + k], h2[j], s);
+    Mh[k] = s;
+}
+
+// nuw: nu, the break test, hw, ||xi||_A^2, and the new row / column of M.
+// h2[0:d] and h2[d] = ||v1||^2; a[0:d] and a[d] = sum w v1^2; Mh = M h2.
+__global__ __launch_bounds__(256) void nuw_kernel(State* __restrict__ st, const double* __restrict__ h2,
+                                                   const double* __restrict__ a, const double* __restrict__ Mh,
+                                                   int d, double* __restrict__ hw, double* __restrict__ M,
+                                                   int64_t ldm) {
+    if (st->stop) return;
+    __shared__ double sred[4];
+    __shared__ int s_ok;
+    __shared__ double s_inv;
+    double q = 0.0, ha = 0.0, hm = 0.0;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        q = fma(h2[k], h2[k], q);
+        ha = fma(h2[k], a[k], ha);
+        hm = fma(h2[k], Mh[k], hm);
+    }
+    q = block_sum(q, sred);
+    ha = block_sum(ha, sred);
+    hm = block_sum(hm, sred);
+    if (threadIdx.x == 0) {
+        const double s = h2[d] - q;
+        const double nu = s > 0.0 ? sqrt(s) : 0.0;
+        st->nu = nu;
+        s_ok = 0;
+        if (nu < st->tau || nu == 0.0) {
+            st->stop = RBD_STOP_BREAK;
+        } else {
+            const double inv = 1.0 / nu;
+            const double wxx = (a[d] - 2.0 * ha + hm) * inv * inv;
+            st->inv_nu = inv;
+            st->wxx = wxx;
+            M[(int64_t)d * ldm + d] = wxx;
+            s_inv = inv;
+            s_ok = 1;
+        }
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const double inv = s_inv;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) {
+        const double h = (a[k] - Mh[k]) * inv;
+        hw[k] = h;
+        M[(int64_t)k * ldm + d] = h;
+        M[(int64_t)d * ldm + k] = h;
+    }
+}
+
+// gvec2: v2 = v1 - Y h2, xi = v2 / nu written to Y(:, d), g = w . xi - Y hw.
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                     const State* __restrict__ st, int d, int rows_per_blk,
+                                                     const double* __restrict__ v1, const double* __restrict__ h2,
+                                                     const double* __restrict__ hw, const double* __restrict__ w,
+                                                     double* __restrict__ v2, double* __restrict__ g) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    __shared__ double gs[KW];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? h2[k] : 0.0;
+        gs[k] = (k < d) ? hw[k] : 0.0;
+    }
+    __syncthreads();
+    const double inv = st->inv_nu;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC];
+        double dots[2 * RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                a = fma(y[u][c], hs[lane + kWave * c], a);
+                b = fma(y[u][c], gs[lane + kWave * c], b);
+            }
+            dots[u] = a;
+            dots[RU + u] = b;
+        }
+        wave_sum_n<2 * RU>(dots);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            if (lane == u && r < r1) {
+                const double v = v1[r] - dots[u];
+                const double xi = v * inv;
+                v2[r] = v;
+                Y[r * ldy + d] = xi;
+                g[r] = w[r] * xi - dots[RU + u];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cgs2: v2 = v1 - Y(:, 0:d) h2 and per-block partial ||v2||^2 (the explicit
+// second pass, kept by the general SPD path, which needs v2 itself for A v2).
+// ---------------------------------------------------------------------------
+template <int KC, int RU>
+__global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                    State* __restrict__ st, int d, int rows_per_blk,
+                                                    const double* __restrict__ v1, const double* __restrict__ h2,
+                                                    double* __restrict__ v2, double* __restrict__ part) {
+    if (st->stop) return;
+    constexpr int KW = kWave * KC;
+    __shared__ double hs[KW];
+    __shared__ double sred[4];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? h2[k] : 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
         double y[RU][KC];
         double vv[RU];
-        double wr[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t r = rb + u;
             const bool ok = r < r1;
             vv[u] = ok ? v1[r] : 0.0;
-            wr[u] = (W && ok) ? w[r] : 0.0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
@@ -449,47 +659,25 @@ __global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y,
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const double v = vv[u] - dot[u];
-            if (W) {
-                const double wv2 = wr[u] * v;            // rows past the end have w = 0
-#pragma unroll
-                for (int c = 0; c < KC; ++c) hacc[W ? c : 0] = fma(y[u][c], wv2, hacc[W ? c : 0]);
-            }
             if (lane == u && rb + u < r1) {
                 v2[rb + u] = v;
                 nacc = fma(v, v, nacc);
-                if (W) wacc = fma(wr[u] * v, v, wacc);
             }
         }
     }
     const double s = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (W) {
-        const double sw = block_sum(wacc, sred);
-        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = sw;
-        if (d > 0) {
-            for (int q = 0; q < nw; ++q) {
-                if (wv == q) {
-#pragma unroll
-                    for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += hacc[W ? c : 0];
-                }
-                __syncthreads();
-            }
-            double* ph = part + 2 * (int64_t)gridDim.x + (int64_t)blockIdx.x * ldp;
-            for (int k = threadIdx.x; k < d; k += blockDim.x) ph[k] = accs[k];
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
-// gvec: g = (A v2 - Y hw) / nu, hw = Y'(A v2), i.e. g = P_d(A xi) with P_d
-// the projector onto the complement of span(Y).  A v2 is w . v2 for a
-// diagonal A (w given), else passed in v2 itself (w = nullptr).
+// gvec (general SPD A): g = (av - Y hw) / nu with av = A v2 and hw = Y'(A v2),
+// i.e. g = P_d(A xi) with P_d the projector onto the complement of span(Y).
 // Then g' x_j drives the weighted downdate of the errors.
 // ---------------------------------------------------------------------------
 template <int KC, int RU>
 __global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
                                                     const State* __restrict__ st, int d, int rows_per_blk,
-                                                    const double* __restrict__ v2, const double* __restrict__ w,
+                                                    const double* __restrict__ av,
                                                     const double* __restrict__ hw, double* __restrict__ g) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
@@ -522,10 +710,7 @@ __global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y,
         wave_sum_n<RU>(dot);
 #pragma unroll
         for (int u = 0; u < RU; ++u)
-            if (lane == u && rb + u < r1) {
-                const double av = w ? w[rb + u] * v2[rb + u] : v2[rb + u];   // w = nullptr: v2 holds A v2
-                g[rb + u] = (av - dot[u]) * inv;
-            }
+            if (lane == u && rb + u < r1) g[rb + u] = (av[rb + u] - dot[u]) * inv;
     }
 }
 
@@ -730,26 +915,17 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
 // nu: nu = ||v2|| from the cgs2 partials (one block, fixed order) and step
 // 2.2's test: ||v|| < eps_R (or ||v|| = 0) keeps the d vectors found so far.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S,
-                                                  int weighted) {
+__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S) {
     if (st->stop) return;
     __shared__ double sred[4];
-    double s = 0.0, sw = 0.0;
-    for (int i = threadIdx.x; i < S; i += blockDim.x) {
-        s += part[i];
-        if (weighted) sw += part[S + i];
-    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < S; i += blockDim.x) s += part[i];
     s = block_sum(s, sred);
-    if (weighted) sw = block_sum(sw, sred);
     if (threadIdx.x == 0) {
         const double nu = sqrt(s);
         st->nu = nu;
-        if (nu < st->tau || nu == 0.0) {
-            st->stop = RBD_STOP_BREAK;
-        } else {
-            st->inv_nu = 1.0 / nu;
-            st->wxx = weighted ? sw / s : 0.0;     // ||v2||_A^2 / ||v2||^2 = ||xi||_A^2
-        }
+        if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
+        else st->inv_nu = 1.0 / nu;
     }
 }
 
