@@ -129,10 +129,11 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_M = take(8 * (size_t)std::max(P->D, 1) * std::max(P->D, 1));    // Y'WY (diagonal A)
     P->o_mh = take(8 * ((size_t)RBD_MAX_D + 1));
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
-    // scan partials (two rows of n per slab with a diagonal A-norm); Gram-Schmidt partials
-    // (the lagged path adds up to ceil(D / kTcorr) correction rows after the scan's slabs)
+    // scan partials (two rows of n per slab with an A-norm); Gram-Schmidt partials.  The
+    // lagged path (rows of n) and the SPD path (rows of 2n) add up to ceil(D / kTcorr)
+    // correction rows after the scan's slabs.
     const size_t kp_max = (size_t)cdiv(std::max(P->D, 1), kTcorr);
-    const size_t part_elems = std::max<size_t>(std::max<size_t>((size_t)P->sc_S * 2 * n, ((size_t)P->sc_S + kp_max) * n),
+    const size_t part_elems = std::max<size_t>(((size_t)P->sc_S + kp_max) * 2 * n,
                                                (size_t)P->cg_S * 2 * (std::max(P->D, 1) + 1));
     P->o_part = take(8 * part_elems);
     const size_t l2_elems =
@@ -291,15 +292,10 @@ void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d,
 }
 
 template <int KC>
-void launch_cgs2(const FitPlan& P, const double* Y, State* st, int d, const double* v1, const double* h2,
-                 double* v2, double* part, hipStream_t s) {
-    cgs2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, v2, part);
-}
-
-template <int KC>
-void launch_gvec(const FitPlan& P, const double* Y, const State* st, int d, const double* av, const double* hw,
-                 double* g, hipStream_t s) {
-    gvec_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, av, hw, g);
+void launch_cgs2u(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
+                  const double* u, double* v2, double* part, hipStream_t s) {
+    cgs2u_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, u, v2, part,
+                                                                 std::max(P.D, 1));
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
@@ -533,13 +529,6 @@ bool make_spd_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, SpdPlan* P
     return true;
 }
 
-template <int KC>
-void launch_ytu(const FitPlan& P, const double* Y, const State* st, int d, const double* u, const double* v2,
-                double* part, hipStream_t s) {
-    ytu_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, u, v2, part,
-                                                               std::max(P.D, 1));
-}
-
 template <typename Tx>
 int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol, int rel, int64_t start, double* Y,
                   double* T, int64_t* pivots, double* col_err, double* err_hist, int32_t* d_out, int32_t* status,
@@ -561,6 +550,9 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
     double* hw = reinterpret_cast<double*>(ws + P.o_hw);
     double* xp = reinterpret_cast<double*>(ws + P.o_xp);
     double* u = reinterpret_cast<double*>(ws + Q.o_u);
+    double* Ma = reinterpret_cast<double*>(ws + P.o_M);      // M = Y'AY
+    double* mh = reinterpret_cast<double*>(ws + P.o_mh);
+    double* const yu = h2 + RBD_MAX_D + 1;                     // Y'(A v1) and v1'A v1
     double* rbuf = reinterpret_cast<double*>(ws + Q.o_rbuf);
     double* qpart = reinterpret_cast<double*>(ws + Q.o_qpart);
     const int64_t nw = 2 * P.n;
@@ -589,6 +581,8 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_INIT, s);
 
+    const int64_t ldp = std::max(P.D, 1);
+    const unsigned sp_grid = (unsigned)std::min<int64_t>(16384, cdiv(P.m, 256));
     for (int d = 0; d < P.D; ++d) {
         const int kc = kc_for(d);
         prof_begin(RBD_PHASE_CGS1, s);
@@ -601,55 +595,51 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
             default: launch_cgs1<16>(P, xp, Y, T, st, d, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
-        if (d > 0) {
-            launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d, l2, h2, 0, s);
-            RBD_LAUNCH_CHECK();
-        }
+        launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, h2, 0, s);
+        RBD_LAUNCH_CHECK();
+        nu_lag_kernel<<<1, 256, 0, s>>>(st, h2, d);
+        RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
-        switch (kc) {
-            case 1: launch_cgs2<1>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 2: launch_cgs2<2>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 4: launch_cgs2<4>(P, Y, st, d, v1, h2, v2, part, s); break;
-            case 8: launch_cgs2<8>(P, Y, st, d, v1, h2, v2, part, s); break;
-            default: launch_cgs2<16>(P, Y, st, d, v1, h2, v2, part, s); break;
-        }
-        RBD_LAUNCH_CHECK();
-        nu_kernel<<<1, 256, 0, s>>>(st, part, P.cg_S);
-        RBD_LAUNCH_CHECK();
-        // u = A v2; hw = Y'u and v2'u; g = P_d(A xi); ||xi||_A^2
-        spmv_kernel<<<(unsigned)std::min<int64_t>(16384, cdiv(P.m, 256)), 256, 0, s>>>(st, A, P.m, v2, u);
+        // u = A v1; second pass: xi, v2 and Y'u, v1'u; then hw, ||xi||_A^2, M
+        spmv_kernel<false><<<sp_grid, 256, 0, s>>>(st, A, P.m, v1, u);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_ytu<1>(P, Y, st, d, u, v2, part, s); break;
-            case 2: launch_ytu<2>(P, Y, st, d, u, v2, part, s); break;
-            case 4: launch_ytu<4>(P, Y, st, d, u, v2, part, s); break;
-            case 8: launch_ytu<8>(P, Y, st, d, u, v2, part, s); break;
-            default: launch_ytu<16>(P, Y, st, d, u, v2, part, s); break;
+            case 1: launch_cgs2u<1>(P, Y, st, d, v1, h2, u, v2, part, s); break;
+            case 2: launch_cgs2u<2>(P, Y, st, d, v1, h2, u, v2, part, s); break;
+            case 4: launch_cgs2u<4>(P, Y, st, d, v1, h2, u, v2, part, s); break;
+            case 8: launch_cgs2u<8>(P, Y, st, d, v1, h2, u, v2, part, s); break;
+            default: launch_cgs2u<16>(P, Y, st, d, v1, h2, u, v2, part, s); break;
         }
         RBD_LAUNCH_CHECK();
-        launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, hw, 0, s);
+        launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, yu, 0, s);
         RBD_LAUNCH_CHECK();
-        set_wxx_kernel<<<1, 64, 0, s>>>(st, hw, d);
-        RBD_LAUNCH_CHECK();
-        switch (kc) {
-            case 1: launch_gvec<1>(P, Y, st, d, u, hw, g, s); break;
-            case 2: launch_gvec<2>(P, Y, st, d, u, hw, g, s); break;
-            case 4: launch_gvec<4>(P, Y, st, d, u, hw, g, s); break;
-            case 8: launch_gvec<8>(P, Y, st, d, u, hw, g, s); break;
-            default: launch_gvec<16>(P, Y, st, d, u, hw, g, s); break;
+        if (d > 0) {
+            mv_kernel<<<(unsigned)cdiv(d, 256), 256, 0, s>>>(st, Ma, ldp, d, h2, mh);
+            RBD_LAUNCH_CHECK();
         }
+        nuw_kernel<<<1, 256, 0, s>>>(st, h2, yu, mh, d, hw, Ma, ldp);
         RBD_LAUNCH_CHECK();
+        spmv_kernel<true><<<sp_grid, 256, 0, s>>>(st, A, P.m, v2, g);
+        RBD_LAUNCH_CHECK();
+        const int kp = d > 0 ? (int)cdiv(d, kTcorr) : 0;
+        if (kp) {
+            tcorr2_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)kp), 256, 0, s>>>(
+                st, hw, d, T, P.n, P.n, part + (int64_t)P.sc_S * nw);
+            RBD_LAUNCH_CHECK();
+        }
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
-        launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, d, part, vec_ok, nt, s, g);
+        launch_xscan<Tx, kScanDot2>(P, X, ldx, v2, st, Y, -1, part, vec_ok, nt, s, g);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_XSCAN, s);
         prof_begin(RBD_PHASE_UPDATE, s);
-        reduce_rows_kernel<<<dim3((unsigned)cdiv(nw, 256), (unsigned)up_groups), 256, 0, s>>>(st, part, nw, P.sc_S,
-                                                                                             up_per, nw, l2, nw);
+        const int rows = P.sc_S + kp;
+        const int groups = (int)cdiv(rows, up_per);
+        reduce_rows_kernel<<<dim3((unsigned)cdiv(nw, 256), (unsigned)groups), 256, 0, s>>>(st, part, nw, rows, up_per,
+                                                                                          nw, l2, nw);
         RBD_LAUNCH_CHECK();
-        update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, up_groups, tickets, e2, base2, T, P.n, flist,
+        update_kernel<kStepW><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n, flist,
                                                        bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);

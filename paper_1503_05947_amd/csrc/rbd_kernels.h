@@ -19,9 +19,18 @@
 //   ycol          the deferred basis column, when a refresh needs it
 //   resid_mfma    exact ||x_j - Y T(:, j)||^2 of queued columns (FP64 MFMA)
 //   resid_finish  store the exact values, argmax, stop test of step 2.4
-// Diagonal and general SPD A keep the explicit second pass (cgs1, cgs2) and add
-// g = (I - YY')(A xi) (gvec; spmv and ytu for a sparse A), the two-vector
-// X-scan and the weighted downdate (update<kStepW>).
+// Diagonal A (two passes over Y per step, M = Y'WY kept up to date):
+//   gather_col, cgs1w (v1, h2, a = Y'(w . v1), sum w v1^2), reduce x2,
+//   mv (M h2), nuw (nu, break test, hw = Y'(W xi), ||xi||_A^2, new row of M),
+//   gvec2 (Y(:, d) = xi, v2, g = w . xi - Y hw), xscan of xi and g,
+//   reduce, update<kStepW> (e_j^2 -= 2 t_j g'x_j - t_j^2 ||xi||_A^2),
+//   resid_mfma, resid_finish.
+// General SPD A in CSR form (two passes over Y per step, M = Y'AY):
+//   gather_col, cgs1 (v1, h2, ||v1||^2), reduce, nu_lag, spmv (u = A v1),
+//   cgs2u (Y(:, d) = xi, v2, Y'u, v1'u), reduce, mv, nuw, spmv (A xi),
+//   tcorr2 (rows -hw' T(0:d, :)), xscan of xi and A xi, reduce,
+//   update<kStepW>; exact refreshes store residual chunks (resid_mfma in
+//   store mode) and reduce r'Ar with csr_quad.
 //
 // Wide kernels (thousands of workgroups) never synchronise across the grid:
 // a device-scope release fence per workgroup writes back the XCD's L2 and
@@ -327,7 +336,8 @@ __device__ __forceinline__ double lane_bcast(double v, int u) {
 }
 
 // ---------------------------------------------------------------------------
-// cgs1: v1 = x_p - Y(:, 0:d) h1, h1 = T(0:d, p); partial h2 = Y' v1 per block.
+// cgs1: v1 = x_p - Y(:, 0:d) h1, h1 = T(0:d, p); per block the partials of
+// h2 = Y' v1 (part[blk * ldp + k], k < d) and of ||v1||^2 (part[blk * ldp + d]).
 // One wave per row of Y (lanes run along k), RU rows in flight per wave; the
 // wave keeps its share of h2 in registers, so Y is read once.
 // ---------------------------------------------------------------------------
@@ -342,6 +352,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
     __shared__ double accs[KW];
+    __shared__ double sred[4];
     const int p = st->p;
     for (int k = threadIdx.x; k < KW; k += blockDim.x) {
         hs[k] = (k < d) ? T[(int64_t)k * ldt + p] : 0.0;
@@ -354,6 +365,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
     double acc[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
         double y[RU][KC];
         double xv[RU];
@@ -380,9 +392,14 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
             const double v = xv[u] - dot[u];   // rows past the end have y = 0
 #pragma unroll
             for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
-            if (lane == u && rb + u < r1) v1[rb + u] = v;
+            if (lane == u && rb + u < r1) {
+                v1[rb + u] = v;
+                nacc = fma(v, v, nacc);
+            }
         }
     }
+    const double nn = block_sum(nacc, sred);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
     if (d == 0) return;
     for (int q = 0; q < nw; ++q) {
         if (w == q) {
@@ -616,102 +633,90 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
 }
 
 // ---------------------------------------------------------------------------
-// cgs2: v2 = v1 - Y(:, 0:d) h2 and per-block partial ||v2||^2 (the explicit
-// second pass, kept by the general SPD path, which needs v2 itself for A v2).
+// General SPD A, two passes over Y per step.  After the first pass (cgs1:
+// v1, h2 = Y'v1, ||v1||^2) and u = A v1, the second pass forms
+// v2 = v1 - Y h2 and xi = v2 / nu (written to Y(:, d)) and, in the same read
+// of Y, the partials of Y'u and v1'u.  With M = Y'AY kept up to date,
+//   hw = Y'(A xi) = (Y'u - M h2) / nu,
+//   ||xi||_A^2 = (v1'u - 2 h2'(Y'u) + h2'M h2) / nu^2
+// (the algebra of the diagonal case, with A v1 in place of w . v1).
+// A xi = (A v2) / nu comes from a second sparse product, and
+// g' x_j = (A xi)' x_j - hw' T(0:d, j) from the scan of A xi plus correction
+// rows through T, so g itself is never formed.
 // ---------------------------------------------------------------------------
-template <int KC, int RU>
-__global__ __launch_bounds__(256) void cgs2_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
-                                                    State* __restrict__ st, int d, int rows_per_blk,
-                                                    const double* __restrict__ v1, const double* __restrict__ h2,
-                                                    double* __restrict__ v2, double* __restrict__ part) {
-    if (st->stop) return;
-    constexpr int KW = kWave * KC;
-    __shared__ double hs[KW];
-    __shared__ double sred[4];
-    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? h2[k] : 0.0;
-    __syncthreads();
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
-    double nacc = 0.0;
-    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
-        double y[RU][KC];
-        double vv[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = rb + u;
-            const bool ok = r < r1;
-            vv[u] = ok ? v1[r] : 0.0;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
-            }
-        }
-        double dot[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            dot[u] = 0.0;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
-        }
-        wave_sum_n<RU>(dot);
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const double v = vv[u] - dot[u];
-            if (lane == u && rb + u < r1) {
-                v2[rb + u] = v;
-                nacc = fma(v, v, nacc);
-            }
-        }
-    }
-    const double s = block_sum(nacc, sred);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
 
-// ---------------------------------------------------------------------------
-// gvec (general SPD A): g = (av - Y hw) / nu with av = A v2 and hw = Y'(A v2),
-// i.e. g = P_d(A xi) with P_d the projector onto the complement of span(Y).
-// Then g' x_j drives the weighted downdate of the errors.
-// ---------------------------------------------------------------------------
+// cgs2u: v2 = v1 - Y h2 (stored), Y(:, d) = v2 / nu; per block the partials
+// of Y'u (part[blk * ldp + k], k < d) and of v1'u (part[blk * ldp + d]).
 template <int KC, int RU>
-__global__ __launch_bounds__(256) void gvec_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
-                                                    const State* __restrict__ st, int d, int rows_per_blk,
-                                                    const double* __restrict__ av,
-                                                    const double* __restrict__ hw, double* __restrict__ g) {
+__global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                     const State* __restrict__ st, int d, int rows_per_blk,
+                                                     const double* __restrict__ v1, const double* __restrict__ h2,
+                                                     const double* __restrict__ u, double* __restrict__ v2,
+                                                     double* __restrict__ part, int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
-    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < d) ? hw[k] : 0.0;
+    __shared__ double accs[KW];
+    __shared__ double sred[4];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? h2[k] : 0.0;
+        accs[k] = 0.0;
+    }
     __syncthreads();
     const double inv = st->inv_nu;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double acc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
         double y[RU][KC];
+        double vv[RU], ur[RU], dot[RU];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = rb + u;
+        for (int q = 0; q < RU; ++q) {
+            const int64_t r = rb + q;
             const bool ok = r < r1;
+            vv[q] = ok ? v1[r] : 0.0;
+            ur[q] = ok ? u[r] : 0.0;
+            dot[q] = 0.0;
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+                y[q][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
             }
         }
-        double dot[RU];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            dot[u] = 0.0;
+        for (int q = 0; q < RU; ++q)
 #pragma unroll
-            for (int c = 0; c < KC; ++c) dot[u] = fma(y[u][c], hs[lane + kWave * c], dot[u]);
-        }
+            for (int c = 0; c < KC; ++c) {
+                dot[q] = fma(y[q][c], hs[lane + kWave * c], dot[q]);
+                acc[c] = fma(y[q][c], ur[q], acc[c]);
+            }
         wave_sum_n<RU>(dot);
 #pragma unroll
-        for (int u = 0; u < RU; ++u)
-            if (lane == u && rb + u < r1) g[rb + u] = (av[rb + u] - dot[u]) * inv;
+        for (int q = 0; q < RU; ++q) {
+            const int64_t r = rb + q;
+            if (lane == q && r < r1) {
+                const double v = vv[q] - dot[q];
+                v2[r] = v;
+                Y[r * ldy + d] = v * inv;
+                nacc = fma(vv[q], ur[q], nacc);
+            }
+        }
     }
+    const double s = block_sum(nacc, sred);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = s;
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (wv == q) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += acc[c];
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -857,6 +862,23 @@ __global__ __launch_bounds__(256) void tcorr_kernel(const State* __restrict__ st
     out[(int64_t)blockIdx.y * n + j] = -c * st->inv_nu;
 }
 
+// tcorr2: rows of 2n for the two-vector scan: zeros in the first n, then
+// -hw' T(k0:k1, :) for a chunk of kTcorr rows of T (hw already divided by nu).
+__global__ __launch_bounds__(256) void tcorr2_kernel(const State* __restrict__ st, const double* __restrict__ hw,
+                                                      int d, const double* __restrict__ T, int64_t ldt, int64_t n,
+                                                      double* __restrict__ out) {
+    if (st->stop) return;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int k0 = blockIdx.y * kTcorr, k1 = min(d, k0 + kTcorr);
+    double c = 0.0;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) c = fma(hw[k], T[(int64_t)k * ldt + j], c);
+    double* row = out + (int64_t)blockIdx.y * 2 * n;
+    row[j] = 0.0;
+    row[n + j] = -c;
+}
+
 // ycol: writes the deferred column, Y(:, col) = (v1 - Y(:, 0:col) h2) / nu.
 // FINAL = false: col = d, before an exact refresh of this step (skipped when
 // none is queued).  FINAL = true: col = (final d) - 1, after the loop; the
@@ -911,23 +933,6 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
     }
 }
 
-// ---------------------------------------------------------------------------
-// nu: nu = ||v2|| from the cgs2 partials (one block, fixed order) and step
-// 2.2's test: ||v|| < eps_R (or ||v|| = 0) keeps the d vectors found so far.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void nu_kernel(State* __restrict__ st, const double* __restrict__ part, int S) {
-    if (st->stop) return;
-    __shared__ double sred[4];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < S; i += blockDim.x) s += part[i];
-    s = block_sum(s, sred);
-    if (threadIdx.x == 0) {
-        const double nu = sqrt(s);
-        st->nu = nu;
-        if (nu < st->tau || nu == 0.0) st->stop = RBD_STOP_BREAK;
-        else st->inv_nu = 1.0 / nu;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // reduce_rows: out[g * ldo + c] = sum over rows r of group g (rows g*per ..
@@ -1184,10 +1189,12 @@ __global__ __launch_bounds__(256) void csr_xax_kernel(const Tx* __restrict__ X, 
     if (j < n) part[(int64_t)blockIdx.y * n + j] = acc;
 }
 
-// spmv: u = A v (one row per thread)
+// spmv: u = A v, or u = (A v) / nu with SCALED (one row per thread)
+template <bool SCALED>
 __global__ __launch_bounds__(256) void spmv_kernel(const State* __restrict__ st, Csr A, int64_t m,
                                                     const double* __restrict__ v, double* __restrict__ u) {
     if (st->stop) return;
+    const double sc = SCALED ? st->inv_nu : 1.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         int64_t e0, e1;
@@ -1197,62 +1204,8 @@ __global__ __launch_bounds__(256) void spmv_kernel(const State* __restrict__ st,
             const int64_t k = A.ix[e];
             if (k >= 0 && k < m) y = fma(A.av[e], v[k], y);
         }
-        u[i] = y;
+        u[i] = SCALED ? y * sc : y;
     }
-}
-
-// ytu: per block, part[blk * ldp + k] = sum_i Y[i, k] u_i (k < d) and
-// part[blk * ldp + d] = sum_i v2_i u_i -- the inputs of g = P_d(A xi) and of
-// ||xi||_A^2.  Same row layout as the Gram-Schmidt passes.
-template <int KC, int RU>
-__global__ __launch_bounds__(256) void ytu_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m,
-                                                   const State* __restrict__ st, int d, int rows_per_blk,
-                                                   const double* __restrict__ u, const double* __restrict__ v2,
-                                                   double* __restrict__ part, int64_t ldp) {
-    if (st->stop) return;
-    constexpr int KW = kWave * KC;
-    __shared__ double accs[KW];
-    __shared__ double sred[4];
-    for (int k = threadIdx.x; k < KW; k += blockDim.x) accs[k] = 0.0;
-    __syncthreads();
-    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
-    double acc[KC];
-#pragma unroll
-    for (int c = 0; c < KC; ++c) acc[c] = 0.0;
-    double s = 0.0;
-    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
-#pragma unroll
-        for (int q = 0; q < RU; ++q) {
-            const int64_t r = rb + q;
-            const bool ok = r < r1;
-            const double ur = ok ? u[r] : 0.0;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                const int k = lane + kWave * c;
-                if (ok && k < d) acc[c] = fma(Y[r * ldy + k], ur, acc[c]);
-            }
-            if (lane == q && ok) s = fma(v2[r], ur, s);
-        }
-    }
-    const double st2 = block_sum(s, sred);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = st2;
-    if (d == 0) return;
-    for (int q = 0; q < nw; ++q) {
-        if (wv == q) {
-#pragma unroll
-            for (int c = 0; c < KC; ++c) accs[lane + kWave * c] += acc[c];
-        }
-        __syncthreads();
-    }
-    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
-}
-
-// wxx = ||xi||_A^2 = (v2' A v2) / nu^2, from hw[d] = v2' u
-__global__ void set_wxx_kernel(State* __restrict__ st, const double* __restrict__ hw, int d) {
-    if (st->stop) return;
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->wxx = hw[d] * st->inv_nu * st->inv_nu;
 }
 
 // csr_quad: part[slab * ldp + c0 + jj] = sum_{i in slab} r_i,jj (A r_jj)_i for
