@@ -159,17 +159,18 @@ int rbd_fit_graph_destroy(rbd_fit_graph graph);
  * symmetric positive definite A, which can couple different entries of a
  * column (for instance an energy norm of a field on a grid), A given in CSR
  * form:
- *   a_indptr   m + 1 int64 row offsets into a_indices / a_values
+ *   a_indptr   m + 1 int64 row offsets into a_indices / a_values,
+ *              non-decreasing (rows own consecutive ranges of entries)
  *   a_indices  a_nnz int32 column indices in [0, m)
  *   a_values   a_nnz FP64 values
  * The basis Y and T = Y'X are built exactly as by rbd_fit; every error of step
  * 2.3 (E_0, the relative tolerance, the argmax, col_err, err_hist) is
  * ||x_j - Y T(:, j)||_A = sqrt(r' A r), eq. (3).  Symmetry and definiteness
- * of A are the caller's responsibility; an index outside [0, m) or a row
- * range outside [0, a_nnz) is skipped by every kernel and reported through
- * *status as RBD_EMATRIX (d = 0).
+ * of A are the caller's responsibility; a column index outside [0, m), a
+ * row range outside [0, a_nnz) or a decreasing a_indptr is reported through
+ * *status as RBD_EMATRIX (d = 0), and no kernel reads outside the arrays.
  * The errors are downdated as for a diagonal A with g = (I - YY')(A xi)
- * (one sparse product per step).  Unlike rbd_fit, this entry point
+ * (two sparse products per step).  Unlike rbd_fit, this entry point
  * synchronises its stream once per greedy step: exact refreshes of queued
  * columns materialise their residuals in chunks, and the host reads the
  * queue length to launch them.  Other arguments, outputs and errors are

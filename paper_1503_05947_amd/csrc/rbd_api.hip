@@ -511,8 +511,8 @@ bool make_spd_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, SpdPlan* P
     if (!make_fit_plan(m, n, d_max, xt, &P->F)) return false;
     P->q_rows = (int)std::max<int64_t>(64, cdiv(m, 2048));
     P->q_S = (int)cdiv(m, P->q_rows);
-    // residual chunk: about 512 MB of FP64 columns, 64 .. 1024 of them
-    int64_t c = ((int64_t)1 << 29) / (8 * m);
+    // residual chunk: about 2 GB of FP64 columns, 64 .. 1024 of them
+    int64_t c = ((int64_t)1 << 31) / (8 * m);
     c = std::max<int64_t>(64, std::min<int64_t>(1024, c / 64 * 64));
     c = std::min<int64_t>(c, cdiv(n, 64) * 64);
     P->cq = (int)c;

@@ -1145,9 +1145,10 @@ __global__ __launch_bounds__(256) void resid_finish_kernel(State* __restrict__ s
 
 // ---------------------------------------------------------------------------
 // General SPD A (section 3.2), A in CSR form (indptr int64, indices int32,
-// values FP64).  Every entry index is checked: an index outside [0, m) or
-// [0, nnz) is skipped and raises bad_index (reported as RBD_EMATRIX by the
-// set-up step, which reads every entry once).
+// values FP64).  Every index is checked: a column index outside [0, m) or a
+// row range outside [0, nnz) is skipped; the set-up step, which reads every
+// row range and entry once, raises bad_index for these and for a decreasing
+// indptr (reported as RBD_EMATRIX, and the loop does not start).
 // ---------------------------------------------------------------------------
 struct Csr {
     const int64_t* __restrict__ ip;
@@ -1177,6 +1178,7 @@ __global__ __launch_bounds__(256) void csr_xax_kernel(const Tx* __restrict__ X, 
     for (int64_t i = r0; i < r1; ++i) {
         int64_t e0, e1;
         csr_row(A, i, e0, e1);
+        if (A.ip[i] < 0 || A.ip[i + 1] > A.nnz || A.ip[i + 1] < A.ip[i]) bad = true;
         double y = 0.0;
         for (int64_t e = e0; e < e1; ++e) {
             const int64_t k = A.ix[e];
@@ -1210,27 +1212,67 @@ __global__ __launch_bounds__(256) void spmv_kernel(const State* __restrict__ st,
 
 // csr_quad: part[slab * ldp + c0 + jj] = sum_{i in slab} r_i,jj (A r_jj)_i for
 // the residual columns jj < cnt held in R (m x cnt, leading dimension ldr).
-// Block: 64 columns x kQuadGroups row groups (rows r0 + g, r0 + g + groups,
-// ...), combined in LDS in a fixed order.
+// The sum runs over the slab's nonzeros, r' A r = sum_e a_e r_row(e) r_col(e),
+// so every entry is independent and several are in flight per wave.  The
+// slab's entries are staged in LDS in chunks with the row of each entry
+// (rows of a well-formed CSR matrix own consecutive ranges of entries);
+// lanes run along the 64 columns of the block, so each access to R reads one
+// contiguous row segment.  The kQuadGroups waves take interleaved entries and
+// are combined in LDS in a fixed order.
 constexpr int kQuadGroups = 4;
+constexpr int kQuadChunk = 2048;
 __global__ __launch_bounds__(64 * kQuadGroups) void csr_quad_kernel(const double* __restrict__ R, int64_t ldr, int64_t m,
                                                                     int cnt, Csr A, int rows_per_slab,
                                                                     double* __restrict__ part, int64_t ldp, int c0) {
+    __shared__ int s_row[kQuadChunk];
+    __shared__ int s_col[kQuadChunk];
+    __shared__ double s_val[kQuadChunk];
     __shared__ double red[kQuadGroups][64];
     const int lane = threadIdx.x % 64, grp = threadIdx.x / 64;
     const int jj = blockIdx.x * 64 + lane;
     const int jc = jj < cnt ? jj : cnt - 1;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_slab, r1 = min(m, r0 + (int64_t)rows_per_slab);
+    const int64_t eb = min(A.nnz, max((int64_t)0, A.ip[r0]));
+    const int64_t ee = max(eb, min(A.nnz, A.ip[r1]));
+    const double* __restrict__ Rc = R + jc;
     double acc = 0.0;
-    for (int64_t i = r0 + grp; i < r1; i += kQuadGroups) {
-        int64_t e0, e1;
-        csr_row(A, i, e0, e1);
-        double y = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t k = A.ix[e];
-            if (k >= 0 && k < m) y = fma(A.av[e], R[k * ldr + jc], y);
+    for (int64_t cb = eb; cb < ee; cb += kQuadChunk) {
+        const int ne = (int)min((int64_t)kQuadChunk, ee - cb);
+        for (int t = threadIdx.x; t < ne; t += blockDim.x) {
+            const int64_t k = A.ix[cb + t];
+            s_row[t] = -1;
+            s_col[t] = (k >= 0 && k < m) ? (int)k : -1;
+            s_val[t] = A.av[cb + t];
         }
-        acc = fma(R[i * ldr + jc], y, acc);
+        __syncthreads();
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+            int64_t e0, e1;
+            csr_row(A, i, e0, e1);
+            e0 = max(e0, cb);
+            e1 = min(e1, cb + ne);
+            for (int64_t e = e0; e < e1; ++e) s_row[e - cb] = (int)(i - r0);
+        }
+        __syncthreads();
+        constexpr int G = kQuadGroups, U = 4;
+        int t = grp;
+        for (; t + (U - 1) * G < ne; t += U * G) {
+            double a[U], x[U], y[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int rr = s_row[t + u * G], k = s_col[t + u * G];
+                const bool ok = rr >= 0 && k >= 0;
+                a[u] = ok ? s_val[t + u * G] : 0.0;
+                x[u] = ok ? Rc[(r0 + rr) * ldr] : 0.0;
+                y[u] = ok ? Rc[(int64_t)k * ldr] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc = fma(a[u] * x[u], y[u], acc);
+        }
+        for (; t < ne; t += G) {
+            const int rr = s_row[t], k = s_col[t];
+            if (rr >= 0 && k >= 0) acc = fma(s_val[t] * Rc[(r0 + rr) * ldr], Rc[(int64_t)k * ldr], acc);
+        }
+        __syncthreads();
     }
     red[grp][lane] = acc;
     __syncthreads();

@@ -121,3 +121,14 @@ def test_index_out_of_range_is_reported():
     X = to_device(np.ones((m, 8), dtype=np.float32), "f32")
     with pytest.raises(ValueError):
         rbd.fit(X, tol=0.0, d_max=4, A=device_csr(indptr, indices, np.ones(m)))
+
+
+def test_decreasing_indptr_is_reported():
+    import paper_1503_05947_amd as rbd
+    print("[gpu] spd decreasing indptr", flush=True)
+    m = 64
+    indptr = np.arange(m + 1)
+    indptr[20] = 25                          # row 19 ends after row 20 ends: not a CSR layout
+    X = to_device(np.ones((m, 8), dtype=np.float32), "f32")
+    with pytest.raises(ValueError):
+        rbd.fit(X, tol=0.0, d_max=4, A=device_csr(indptr, np.arange(m), np.ones(m)))
