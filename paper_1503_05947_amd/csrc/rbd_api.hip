@@ -53,7 +53,7 @@ struct FitPlan {
     int ntickets = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
-    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_M, o_mh, o_hw,
+    size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_M, o_mh, o_hw, o_ys,
         o_part,
         o_l2, o_rpart, total;
 };
@@ -129,6 +129,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_M = take(8 * (size_t)std::max(P->D, 1) * std::max(P->D, 1));    // Y'WY (diagonal A)
     P->o_mh = take(8 * ((size_t)RBD_MAX_D + 1));
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
+    P->o_ys = take(8 * 8 * (size_t)m);      // staged deferred columns (A = I), m x 8 column-major
     // scan partials (two rows of n per slab with an A-norm); Gram-Schmidt partials.  The
     // lagged path (rows of n) and the SPD path (rows of 2n) add up to ceil(D / kTcorr)
     // correction rows after the scan's slabs.
@@ -143,6 +144,11 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->total = o;
     return true;
 }
+
+// Passes over Y(:, 0:d) use non-temporal loads once that read exceeds the
+// last-level cache (256 MB): measured on MI355X, a 4 GB row-major Y streams
+// at 6.3 TB/s with ordinary loads and 6.9-7.0 TB/s with non-temporal ones.
+bool y_stream(const FitPlan& P, int d) { return (double)P.m * (double)d * 8.0 > 256.0 * 1024 * 1024; }
 
 int kc_for(int d) {
     const int need = std::max(1, (d + kWave - 1) / kWave);
@@ -241,29 +247,47 @@ constexpr int rows_in_flight(int KC) { return KC <= 2 ? 8 : (KC <= 8 ? 4 : 2); }
 template <int KC>
 void launch_cgs1(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
                  double* v1, double* part, hipStream_t s) {
-    cgs1_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, v1,
-                                                                part, std::max(P.D, 1));
+    if (y_stream(P, d))
+        cgs1_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                          P.cg_rows, v1, part, std::max(P.D, 1));
+    else
+        cgs1_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                           P.cg_rows, v1, part, std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_cgs1w(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
                   const double* w, double* v1, double* part, hipStream_t s) {
-    cgs1w_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows, w, v1,
-                                                                 part, std::max(P.D, 1));
+    if (y_stream(P, d))
+        cgs1w_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                           P.cg_rows, w, v1, part, std::max(P.D, 1));
+    else
+        cgs1w_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                            P.cg_rows, w, v1, part, std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_gvec2(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
                   const double* hw, const double* w, double* v2, double* g, hipStream_t s) {
-    gvec2_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, hw, w, v2,
-                                                                 g);
+    if (y_stream(P, d))
+        gvec2_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
+                                                                           hw, w, v2, g);
+    else
+        gvec2_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
+                                                                            hw, w, v2, g);
 }
 
 template <int KC>
 void launch_cgs1_lag(const FitPlan& P, const double* xp, double* Y, const double* T, State* st, int d,
-                     const double* v1p, const double* h2p, double* v1, double* part, hipStream_t s) {
-    cgs1_lag_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d, P.cg_rows,
-                                                                    v1p, h2p, v1, part, std::max(P.D, 1));
+                     const double* v1p, const double* h2p, double* v1, double* ys, double* part, hipStream_t s) {
+    if (y_stream(P, d))
+        cgs1_lag_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                              P.cg_rows, v1p, h2p, v1, ys, part,
+                                                                              std::max(P.D, 1));
+    else
+        cgs1_lag_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+                                                                               P.cg_rows, v1p, h2p, v1, ys, part,
+                                                                               std::max(P.D, 1));
 }
 
 template <typename Tx>
@@ -274,28 +298,37 @@ void launch_gather(const FitPlan& P, const Tx* X, int64_t ldx, const State* st, 
 
 template <int KC, bool FINAL>
 void launch_ycol(const FitPlan& P, double* Y, const State* st, int d, const double* v1a, const double* v1b,
-                 const double* h2a, const double* h2b, hipStream_t s) {
-    ycol_kernel<KC, rows_in_flight(KC), FINAL><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1a, v1b,
-                                                                       h2a, h2b);
+                 const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
+    // FINAL: the column index is only known on the device; size the choice by D
+    if (y_stream(P, FINAL ? P.D : d))
+        ycol_kernel<KC, rows_in_flight(KC), FINAL, true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
+                                                                                 v1a, v1b, h2a, h2b, ys);
+    else
+        ycol_kernel<KC, rows_in_flight(KC), FINAL, false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
+                                                                                  v1a, v1b, h2a, h2b, ys);
 }
 
 template <bool FINAL>
 void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d, const double* v1a,
-                    const double* v1b, const double* h2a, const double* h2b, hipStream_t s) {
+                    const double* v1b, const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
     switch (kc) {
-        case 1: launch_ycol<1, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
-        case 2: launch_ycol<2, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
-        case 4: launch_ycol<4, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
-        case 8: launch_ycol<8, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
-        default: launch_ycol<16, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, s); break;
+        case 1: launch_ycol<1, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 2: launch_ycol<2, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 4: launch_ycol<4, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 8: launch_ycol<8, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        default: launch_ycol<16, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
     }
 }
 
 template <int KC>
 void launch_cgs2u(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
                   const double* u, double* v2, double* part, hipStream_t s) {
-    cgs2u_kernel<KC, rows_in_flight(KC)><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2, u, v2, part,
-                                                                 std::max(P.D, 1));
+    if (y_stream(P, d))
+        cgs2u_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
+                                                                           u, v2, part, std::max(P.D, 1));
+    else
+        cgs2u_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1,
+                                                                            h2, u, v2, part, std::max(P.D, 1));
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
@@ -330,6 +363,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     double* xp = reinterpret_cast<double*>(ws + P.o_xp);
     double* Mw = reinterpret_cast<double*>(ws + P.o_M);
     double* mh = reinterpret_cast<double*>(ws + P.o_mh);
+    double* ys = reinterpret_cast<double*>(ws + P.o_ys);
     const bool W = (w != nullptr);
     const int64_t nw = W ? 2 * P.n : P.n;     // scan partial row length
 
@@ -370,11 +404,11 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs1_lag<1>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 2: launch_cgs1_lag<2>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 4: launch_cgs1_lag<4>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            case 8: launch_cgs1_lag<8>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
-            default: launch_cgs1_lag<16>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], part, s); break;
+            case 1: launch_cgs1_lag<1>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 2: launch_cgs1_lag<2>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 4: launch_cgs1_lag<4>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 8: launch_cgs1_lag<8>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            default: launch_cgs1_lag<16>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
@@ -406,7 +440,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
         // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
-        launch_ycol_kc<false>(kc, P, Y, st, d, v1s[0], v1s[1], h2s[0], h2s[1], s);
+        launch_ycol_kc<false>(kc, P, Y, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
         RBD_LAUNCH_CHECK();
         resid_mfma_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, nullptr);
@@ -484,7 +518,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     prof_begin(RBD_PHASE_EPILOGUE, s);
     if (!W) {
         // the last basis vector is still implicit: write it
-        launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], s);
+        launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], ys,
+                             s);
         RBD_LAUNCH_CHECK();
     }
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,

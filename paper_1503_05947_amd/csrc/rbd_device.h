@@ -14,6 +14,15 @@
 
 namespace rbd {
 
+// One element of Y in a pass over its rows.  NT: a non-temporal load, for
+// passes whose Y is larger than the caches (Y is read once per greedy step,
+// so nothing it would keep in the caches is used again).
+template <bool NT>
+__device__ __forceinline__ double ld_y(const double* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 constexpr int kWave = 64;
 constexpr int kStopError = 4;           // internal stop code: non-finite input
 constexpr double kRefresh = 0x1p-20;    // kappa: re-evaluate a column exactly when e^2 < kappa * (last exact e^2)
@@ -113,28 +122,75 @@ __device__ __forceinline__ double dpp_add(double v) {
     return v + __hiloint2double(hi, lo);
 }
 
-// Sums of R independent values over the 64 lanes of a wave, interleaved step
-// by step; the result is uniform (read from lane 63).  Fixed order: quads,
-// half rows, rows of 16, then rows 0+1 and 2+3, then the two halves.
+// A DPP move of a double (two 32-bit halves); every lane of the row receives.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Butterfly steps across rows with the gfx950 lane swaps.  bfly32: lanes 0-31
+// get a(l) + a(l + 32), lanes 32-63 get b(l - 32) + b(l).  bfly16: rows 0 and
+// 2 get a summed over the row pairs (0, 1) and (2, 3), rows 1 and 3 get b.
+__device__ __forceinline__ double bfly32(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double bfly16(double a, double b) {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// Within rows: lanes whose bit B is 0 keep a, the others b, and each adds its
+// partner's copy (CTRL pairs every lane with one whose bit B differs).
+template <int CTRL, int B>
+__device__ __forceinline__ double bfly_row(double a, double b, int lane) {
+    const bool up = (lane >> B) & 1;
+    const double keep = up ? b : a, send = up ? a : b;
+    return keep + dpp_mov<CTRL>(send);
+}
+
+// Sums of R independent values (R = 1, 2, 4, 8 or 16) over the 64 lanes of a
+// wave, results uniform.  A transposing butterfly: each of the first log2(R)
+// levels halves the values a lane carries (lanes 32 apart, then 16, 8, 4), so
+// the step count does not grow with R; value u ends up in lanes
+// [u * 64 / R, (u + 1) * 64 / R).  The pairing order (bit 5, 4, 3, then the
+// half-row mirror, then bits 1 and 0) is the same for every value and every R,
+// so a value's sum does not depend on how many are reduced with it.
 // Every lane of the wave must be active.
 template <int R>
 __device__ __forceinline__ void wave_sum_n(double (&v)[R]) {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16, "R must be a power of two up to 16");
+    const int lane = __lane_id();
+    if constexpr (R >= 2) {
 #pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0xB1, 0xf>(v[u]);   // quad_perm [1,0,3,2]
+        for (int j = 0; j < R / 2; ++j) v[j] = bfly32(v[j], v[j + R / 2]);
+    } else {
+        v[0] = bfly32(v[0], v[0]);
+    }
+    if constexpr (R >= 4) {
 #pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x4E, 0xf>(v[u]);   // quad_perm [2,3,0,1]
+        for (int j = 0; j < R / 4; ++j) v[j] = bfly16(v[j], v[j + R / 4]);
+    } else {
+        v[0] = bfly16(v[0], v[0]);
+    }
+    if constexpr (R >= 8) {
 #pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x141, 0xf>(v[u]);  // row_half_mirror
-#pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x140, 0xf>(v[u]);  // row_mirror
-#pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x142, 0xa>(v[u]);  // row_bcast:15
-#pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = dpp_add<0x143, 0xc>(v[u]);  // row_bcast:31
+        for (int j = 0; j < R / 8; ++j) v[j] = bfly_row<0x128, 3>(v[j], v[j + R / 8], lane);   // row_ror:8
+    } else {
+        v[0] = dpp_add<0x128, 0xf>(v[0]);
+    }
+    if constexpr (R >= 16) v[0] = bfly_row<0x141, 2>(v[0], v[1], lane);                       // row_half_mirror
+    else v[0] = dpp_add<0x141, 0xf>(v[0]);
+    v[0] = dpp_add<0x4E, 0xf>(v[0]);   // quad_perm [2,3,0,1]
+    v[0] = dpp_add<0xB1, 0xf>(v[0]);   // quad_perm [1,0,3,2]
+    const double s = v[0];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v[u]), 63);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v[u]), 63);
+        const int lo = __builtin_amdgcn_readlane(__double2loint(s), u * (64 / R));
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(s), u * (64 / R));
         v[u] = __hiloint2double(hi, lo);
     }
 }

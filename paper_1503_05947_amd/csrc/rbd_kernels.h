@@ -341,7 +341,7 @@ __device__ __forceinline__ double lane_bcast(double v, int u) {
 // One wave per row of Y (lanes run along k), RU rows in flight per wave; the
 // wave keeps its share of h2 in registers, so Y is read once.
 // ---------------------------------------------------------------------------
-template <int KC, int RU>
+template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp, int64_t m,
                                                     const double* __restrict__ Y, int64_t ldy,
                                                     const double* __restrict__ T, int64_t ldt,
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
             }
         }
 #pragma unroll
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
 // cgs1w: v1 = x_p - Y h1 as in cgs1, with per-block partials of h2 = Y'v1
 // and ||v1||^2 (part[blk * ldp + k], k <= d) and of a = Y'(w . v1) and
 // sum w v1^2 (the same layout, gridDim.x * ldp further on).
-template <int KC, int RU>
+template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ xp, int64_t m,
                                                      const double* __restrict__ Y, int64_t ldy,
                                                      const double* __restrict__ T, int64_t ldt,
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ x
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
             }
         }
 #pragma unroll
@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) void nuw_kernel(State* __restrict__ st, const 
 }
 
 // gvec2: v2 = v1 - Y h2, xi = v2 / nu written to Y(:, d), g = w . xi - Y hw.
-template <int KC, int RU>
+template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
                                                      const State* __restrict__ st, int d, int rows_per_blk,
                                                      const double* __restrict__ v1, const double* __restrict__ h2,
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
             }
         }
 #pragma unroll
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
 
 // cgs2u: v2 = v1 - Y h2 (stored), Y(:, d) = v2 / nu; per block the partials
 // of Y'u (part[blk * ldp + k], k < d) and of v1'u (part[blk * ldp + d]).
-template <int KC, int RU>
+template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
                                                      const State* __restrict__ st, int d, int rows_per_blk,
                                                      const double* __restrict__ v1, const double* __restrict__ h2,
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[q][c] = (ok && k < d) ? Y[r * ldy + k] : 0.0;
+                y[q][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
             }
         }
 #pragma unroll
@@ -729,20 +729,29 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 // Y anyway; so each step reads Y once instead of twice.
 // ---------------------------------------------------------------------------
 
+// Deferred columns are staged.  Writing one column of row-major Y costs a
+// partial cache-line write per row (measured: a quarter of the pass's time at
+// m = 2^20), so column c goes to slot c % 8 of ys (m x 8, column-major,
+// contiguous per slot) and reaches Y when its block of 8 columns is complete,
+// as one 64-byte segment per row.  Columns below 8 floor(c / 8) are in Y;
+// columns [8 floor(c / 8), c) only in ys.  ycol copies the staged columns into
+// Y wherever Y must be complete (before an exact refresh, after the loop).
+
 // cgs1_lag: first forms this row's entry of the deferred column d-1,
 //   Y(i, d-1) = (v1p_i - Y(i, 0:d-1) h2p) / nu_prev,
-// stores it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
+// stages it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
 // share of h2 = Y(:, 0:d)' v1 (part[blk*ldp + k], k < d) and of ||v1||^2
 // (part[blk*ldp + d]).
-template <int KC, int RU>
+template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict__ xp, int64_t m,
                                                         double* __restrict__ Y, int64_t ldy,
                                                         const double* __restrict__ T, int64_t ldt,
                                                         State* __restrict__ st, int d, int rows_per_blk,
                                                         const double* __restrict__ v1p,
                                                         const double* __restrict__ h2p, double* __restrict__ v1,
-                                                        double* __restrict__ part, int64_t ldp) {
-    static_assert(RU <= kWave, "one lane per row in flight");
+                                                        double* __restrict__ ys, double* __restrict__ part,
+                                                        int64_t ldp) {
+    static_assert(RU <= kWave / 8, "eight lanes per row in flight for the block write");
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -761,6 +770,9 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
     const double hl = dl >= 0 ? hs[dl] : 0.0;
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
     const int cl = dl >= 0 ? dl / kWave : -1, ll = dl >= 0 ? dl % kWave : -1;
+    const int yb = dl >= 0 ? (dl & ~7) : 0;       // columns below yb are in Y, [yb, dl) in ys
+    const bool blk = dl >= 0 && (dl & 7) == 7;    // this column completes its block
+    const int ju = lane >> 3, jj = lane & 7;       // lane 8u + j writes Y(rb + u, yb + j)
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     double acc[KC];
@@ -773,6 +785,8 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         const bool okl = lane < RU && rl < r1;
         const double xl = okl ? xp[rl] : 0.0;
         const double vl = (okl && dl >= 0) ? v1p[rl] : 0.0;
+        const bool okb = blk && ju < RU && rb + ju < r1;
+        const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
         double y[RU][KC];
         double dots[2 * RU];
 #pragma unroll
@@ -782,7 +796,8 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < dl) ? Y[r * ldy + k] : 0.0;
+                const double* src = k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
+                y[u][c] = (ok && k < dl) ? ld_y<NT>(src) : 0.0;
             }
         }
 #pragma unroll
@@ -797,7 +812,7 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
             dots[RU + u] = b;
         }
         wave_sum_n<2 * RU>(dots);
-        double vo = 0.0, yo = 0.0;
+        double vo = 0.0, yo = 0.0, yb7 = 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const double yl = dl >= 0 ? (lane_bcast(vl, u) - dots[u]) * invp : 0.0;   // rows past the end: 0
@@ -808,12 +823,14 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
 #pragma unroll
             for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
             if (lane == u) { vo = v; yo = yl; }
+            if (ju == u) yb7 = yl;
         }
         if (okl) {
             v1[rl] = vo;
             nacc = fma(vo, vo, nacc);
-            if (dl >= 0) Y[rl * ldy + dl] = yo;
+            if (dl >= 0) ys[(int64_t)(dl - yb) * m + rl] = yo;
         }
+        if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : yb7;
     }
     const double nn = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
@@ -879,15 +896,18 @@ __global__ __launch_bounds__(256) void tcorr2_kernel(const State* __restrict__ s
     row[n + j] = -c;
 }
 
-// ycol: writes the deferred column, Y(:, col) = (v1 - Y(:, 0:col) h2) / nu.
+// ycol: writes the deferred column, Y(:, col) = (v1 - Y(:, 0:col) h2) / nu,
+// and copies the staged columns [8 floor(col / 8), col) from ys into Y, so
+// that Y(:, 0:col+1) is complete.
 // FINAL = false: col = d, before an exact refresh of this step (skipped when
 // none is queued).  FINAL = true: col = (final d) - 1, after the loop; the
 // buffers of that step are chosen by the parity of col.
-template <int KC, int RU, bool FINAL>
+template <int KC, int RU, bool FINAL, bool NT>
 __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
                                                     const State* __restrict__ st, int d, int rows_per_blk,
                                                     const double* __restrict__ v1a, const double* __restrict__ v1b,
-                                                    const double* __restrict__ h2a, const double* __restrict__ h2b) {
+                                                    const double* __restrict__ h2a, const double* __restrict__ h2b,
+                                                    const double* __restrict__ ys) {
     int col;
     if (FINAL) {
         if (st->stop == kStopError) return;
@@ -905,6 +925,8 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
     __syncthreads();
     const double inv = st->inv_nu;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int yb = col & ~7;                       // columns below yb are in Y, [yb, col) in ys
+    const int ju = lane >> 3, jj = lane & 7;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
@@ -916,7 +938,8 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < col) ? Y[r * ldy + k] : 0.0;
+                const double* src = k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
+                y[u][c] = (ok && k < col) ? ld_y<NT>(src) : 0.0;
             }
         }
         double dot[RU];
@@ -930,6 +953,8 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
 #pragma unroll
         for (int u = 0; u < RU; ++u)
             if (lane == u && rb + u < r1) Y[(rb + u) * ldy + col] = (v1[rb + u] - dot[u]) * inv;
+        // the staged columns [yb, col) of these rows into Y
+        if (ju < RU && rb + ju < r1 && yb + jj < col) Y[(rb + ju) * ldy + yb + jj] = ys[(int64_t)jj * m + rb + ju];
     }
 }
 
