@@ -246,35 +246,35 @@ constexpr int rows_in_flight(int KC) { return KC <= 2 ? 8 : (KC <= 8 ? 4 : 2); }
 
 template <int KC>
 void launch_cgs1(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
-                 double* v1, double* part, hipStream_t s) {
+                 const double* ys, double* v1, double* part, hipStream_t s) {
     if (y_stream(P, d))
         cgs1_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                          P.cg_rows, v1, part, std::max(P.D, 1));
+                                                                          P.cg_rows, ys, v1, part, std::max(P.D, 1));
     else
         cgs1_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                           P.cg_rows, v1, part, std::max(P.D, 1));
+                                                                           P.cg_rows, ys, v1, part, std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_cgs1w(const FitPlan& P, const double* xp, const double* Y, const double* T, State* st, int d,
-                  const double* w, double* v1, double* part, hipStream_t s) {
+                  const double* w, const double* ys, double* v1, double* part, hipStream_t s) {
     if (y_stream(P, d))
         cgs1w_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                           P.cg_rows, w, v1, part, std::max(P.D, 1));
+                                                                           P.cg_rows, w, ys, v1, part, std::max(P.D, 1));
     else
         cgs1w_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
-                                                                            P.cg_rows, w, v1, part, std::max(P.D, 1));
+                                                                            P.cg_rows, w, ys, v1, part, std::max(P.D, 1));
 }
 
 template <int KC>
 void launch_gvec2(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
-                  const double* hw, const double* w, double* v2, double* g, hipStream_t s) {
+                  const double* hw, const double* w, double* ys, double* v2, double* g, hipStream_t s) {
     if (y_stream(P, d))
         gvec2_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
-                                                                           hw, w, v2, g);
+                                                                           hw, w, ys, v2, g);
     else
         gvec2_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
-                                                                            hw, w, v2, g);
+                                                                            hw, w, ys, v2, g);
 }
 
 template <int KC>
@@ -322,13 +322,20 @@ void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d,
 
 template <int KC>
 void launch_cgs2u(const FitPlan& P, double* Y, const State* st, int d, const double* v1, const double* h2,
-                  const double* u, double* v2, double* part, hipStream_t s) {
+                  const double* u, double* ys, double* v2, double* part, hipStream_t s) {
     if (y_stream(P, d))
         cgs2u_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1, h2,
-                                                                           u, v2, part, std::max(P.D, 1));
+                                                                           u, ys, v2, part, std::max(P.D, 1));
     else
         cgs2u_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows, v1,
-                                                                            h2, u, v2, part, std::max(P.D, 1));
+                                                                            h2, u, ys, v2, part, std::max(P.D, 1));
+}
+
+// the staged basis columns into Y (before an exact refresh: FINAL = false, cols = d + 1)
+template <bool FINAL>
+void launch_ys_flush(const FitPlan& P, double* Y, const State* st, int cols, const double* ys, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(P.m * 8, 256));
+    ys_flush_kernel<FINAL><<<g, 256, 0, s>>>(Y, P.d_max, P.m, st, cols, ys);
 }
 
 // out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
@@ -462,11 +469,11 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs1w<1>(P, xp, Y, T, st, d, w, v1, part, s); break;
-            case 2: launch_cgs1w<2>(P, xp, Y, T, st, d, w, v1, part, s); break;
-            case 4: launch_cgs1w<4>(P, xp, Y, T, st, d, w, v1, part, s); break;
-            case 8: launch_cgs1w<8>(P, xp, Y, T, st, d, w, v1, part, s); break;
-            default: launch_cgs1w<16>(P, xp, Y, T, st, d, w, v1, part, s); break;
+            case 1: launch_cgs1w<1>(P, xp, Y, T, st, d, w, ys, v1, part, s); break;
+            case 2: launch_cgs1w<2>(P, xp, Y, T, st, d, w, ys, v1, part, s); break;
+            case 4: launch_cgs1w<4>(P, xp, Y, T, st, d, w, ys, v1, part, s); break;
+            case 8: launch_cgs1w<8>(P, xp, Y, T, st, d, w, ys, v1, part, s); break;
+            default: launch_cgs1w<16>(P, xp, Y, T, st, d, w, ys, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, h2, 0, s);
@@ -482,11 +489,11 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         nuw_kernel<<<1, 256, 0, s>>>(st, h2, avec, mh, d, hw, Mw, ldp);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_gvec2<1>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
-            case 2: launch_gvec2<2>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
-            case 4: launch_gvec2<4>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
-            case 8: launch_gvec2<8>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
-            default: launch_gvec2<16>(P, Y, st, d, v1, h2, hw, w, v2, g, s); break;
+            case 1: launch_gvec2<1>(P, Y, st, d, v1, h2, hw, w, ys, v2, g, s); break;
+            case 2: launch_gvec2<2>(P, Y, st, d, v1, h2, hw, w, ys, v2, g, s); break;
+            case 4: launch_gvec2<4>(P, Y, st, d, v1, h2, hw, w, ys, v2, g, s); break;
+            case 8: launch_gvec2<8>(P, Y, st, d, v1, h2, hw, w, ys, v2, g, s); break;
+            default: launch_gvec2<16>(P, Y, st, d, v1, h2, hw, w, ys, v2, g, s); break;
         }
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);
@@ -502,6 +509,9 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
+        // an exact refresh of this step needs Y(:, 0:d+1) in Y (skipped when nothing is queued)
+        launch_ys_flush<false>(P, Y, st, d + 1, ys, s);
+        RBD_LAUNCH_CHECK();
         resid_mfma_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, w);
         RBD_LAUNCH_CHECK();
@@ -516,7 +526,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
     const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
     prof_begin(RBD_PHASE_EPILOGUE, s);
-    if (!W) {
+    if (W) {
+        launch_ys_flush<true>(P, Y, st, 0, ys, s);
+        RBD_LAUNCH_CHECK();
+    } else {
         // the last basis vector is still implicit: write it
         launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], ys,
                              s);
@@ -588,6 +601,7 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
     double* Ma = reinterpret_cast<double*>(ws + P.o_M);      // M = Y'AY
     double* mh = reinterpret_cast<double*>(ws + P.o_mh);
     double* const yu = h2 + RBD_MAX_D + 1;                     // Y'(A v1) and v1'A v1
+    double* ys = reinterpret_cast<double*>(ws + P.o_ys);
     double* rbuf = reinterpret_cast<double*>(ws + Q.o_rbuf);
     double* qpart = reinterpret_cast<double*>(ws + Q.o_qpart);
     const int64_t nw = 2 * P.n;
@@ -623,11 +637,11 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         prof_begin(RBD_PHASE_CGS1, s);
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         switch (kc) {
-            case 1: launch_cgs1<1>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 2: launch_cgs1<2>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 4: launch_cgs1<4>(P, xp, Y, T, st, d, v1, part, s); break;
-            case 8: launch_cgs1<8>(P, xp, Y, T, st, d, v1, part, s); break;
-            default: launch_cgs1<16>(P, xp, Y, T, st, d, v1, part, s); break;
+            case 1: launch_cgs1<1>(P, xp, Y, T, st, d, ys, v1, part, s); break;
+            case 2: launch_cgs1<2>(P, xp, Y, T, st, d, ys, v1, part, s); break;
+            case 4: launch_cgs1<4>(P, xp, Y, T, st, d, ys, v1, part, s); break;
+            case 8: launch_cgs1<8>(P, xp, Y, T, st, d, ys, v1, part, s); break;
+            default: launch_cgs1<16>(P, xp, Y, T, st, d, ys, v1, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, h2, 0, s);
@@ -640,11 +654,11 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         spmv_kernel<false><<<sp_grid, 256, 0, s>>>(st, A, P.m, v1, u);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs2u<1>(P, Y, st, d, v1, h2, u, v2, part, s); break;
-            case 2: launch_cgs2u<2>(P, Y, st, d, v1, h2, u, v2, part, s); break;
-            case 4: launch_cgs2u<4>(P, Y, st, d, v1, h2, u, v2, part, s); break;
-            case 8: launch_cgs2u<8>(P, Y, st, d, v1, h2, u, v2, part, s); break;
-            default: launch_cgs2u<16>(P, Y, st, d, v1, h2, u, v2, part, s); break;
+            case 1: launch_cgs2u<1>(P, Y, st, d, v1, h2, u, ys, v2, part, s); break;
+            case 2: launch_cgs2u<2>(P, Y, st, d, v1, h2, u, ys, v2, part, s); break;
+            case 4: launch_cgs2u<4>(P, Y, st, d, v1, h2, u, ys, v2, part, s); break;
+            case 8: launch_cgs2u<8>(P, Y, st, d, v1, h2, u, ys, v2, part, s); break;
+            default: launch_cgs2u<16>(P, Y, st, d, v1, h2, u, ys, v2, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, yu, 0, s);
@@ -685,6 +699,8 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         if (h.stop) break;
         prof_begin(RBD_PHASE_RESID, s);
         if (h.nflag > 0) {
+            launch_ys_flush<false>(P, Y, st, d + 1, ys, s);
+            RBD_LAUNCH_CHECK();
             for (int c0 = 0; c0 < h.nflag; c0 += Q.cq) {
                 const int cc = std::min(Q.cq, h.nflag - c0);
                 const unsigned grid = (unsigned)std::min<int64_t>(2048, cdiv(cc, 64) * P.rc_S);
@@ -710,6 +726,8 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
     const int64_t work = std::max<int64_t>(P.m, P.n) + (int64_t)P.d_max;
     const int eg = (int)std::min<int64_t>(4096, cdiv(work, 256));
     prof_begin(RBD_PHASE_EPILOGUE, s);
+    launch_ys_flush<true>(P, Y, st, 0, ys, s);
+    RBD_LAUNCH_CHECK();
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
                                        stop_reason);
     RBD_LAUNCH_CHECK();

@@ -335,6 +335,44 @@ __device__ __forceinline__ double lane_bcast(double v, int u) {
     return __hiloint2double(hi, lo);
 }
 
+// Staged basis columns.  Writing one column of row-major Y costs a partial
+// cache-line write per row (measured: a quarter of a Gram-Schmidt pass's time
+// at m = 2^20), so a new column c goes to slot c % 8 of ys (m x 8,
+// column-major, contiguous per slot) and reaches Y when its block of 8 is
+// complete, as one 64-byte segment per row.  With c columns formed, columns
+// below 8 floor(c / 8) are in Y and columns [8 floor(c / 8), c) only in ys;
+// ys_flush / ycol copy the staged ones into Y wherever Y must be complete
+// (before an exact refresh, after the loop).
+__device__ __forceinline__ const double* y_src(const double* Y, int64_t ldy, const double* ys, int64_t m, int64_t r,
+                                               int k, int yb) {
+    return k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
+}
+
+// ys_flush: copies the staged columns [8 floor(c / 8), c) into Y, with c the
+// final d (FINAL) or c = cols before an exact refresh (skipped when none is
+// queued).  Eight consecutive threads write the eight entries of one row.
+template <bool FINAL>
+__global__ __launch_bounds__(256) void ys_flush_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
+                                                        const State* __restrict__ st, int cols,
+                                                        const double* __restrict__ ys) {
+    int c;
+    if (FINAL) {
+        if (st->stop == kStopError) return;
+        c = st->d;
+    } else {
+        if (st->stop || st->nflag == 0) return;
+        c = cols;
+    }
+    const int yb = c & ~7, nc = c - yb;
+    if (nc <= 0) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m * 8; t += stride) {
+        const int64_t r = t >> 3;
+        const int j = (int)(t & 7);
+        if (j < nc) Y[r * ldy + yb + j] = ys[(int64_t)j * m + r];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // cgs1: v1 = x_p - Y(:, 0:d) h1, h1 = T(0:d, p); per block the partials of
 // h2 = Y' v1 (part[blk * ldp + k], k < d) and of ||v1||^2 (part[blk * ldp + d]).
@@ -346,8 +384,8 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
                                                     const double* __restrict__ Y, int64_t ldy,
                                                     const double* __restrict__ T, int64_t ldt,
                                                     State* __restrict__ st, int d, int rows_per_blk,
-                                                    double* __restrict__ v1, double* __restrict__ part,
-                                                    int64_t ldp) {
+                                                    const double* __restrict__ ys, double* __restrict__ v1,
+                                                    double* __restrict__ part, int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -360,6 +398,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
     }
     __syncthreads();
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int yb = d & ~7;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     double acc[KC];
@@ -379,7 +418,7 @@ __global__ __launch_bounds__(256) void cgs1_kernel(const double* __restrict__ xp
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
 #pragma unroll
@@ -430,8 +469,9 @@ __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ x
                                                      const double* __restrict__ Y, int64_t ldy,
                                                      const double* __restrict__ T, int64_t ldt,
                                                      State* __restrict__ st, int d, int rows_per_blk,
-                                                     const double* __restrict__ w, double* __restrict__ v1,
-                                                     double* __restrict__ part, int64_t ldp) {
+                                                     const double* __restrict__ w, const double* __restrict__ ys,
+                                                     double* __restrict__ v1, double* __restrict__ part,
+                                                     int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -446,6 +486,7 @@ __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ x
     }
     __syncthreads();
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int yb = d & ~7;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     double acc[KC], acw[KC];
@@ -465,7 +506,7 @@ __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ x
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
 #pragma unroll
@@ -579,7 +620,8 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
                                                      const State* __restrict__ st, int d, int rows_per_blk,
                                                      const double* __restrict__ v1, const double* __restrict__ h2,
                                                      const double* __restrict__ hw, const double* __restrict__ w,
-                                                     double* __restrict__ v2, double* __restrict__ g) {
+                                                     double* __restrict__ ys, double* __restrict__ v2,
+                                                     double* __restrict__ g) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -591,9 +633,16 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
     __syncthreads();
     const double inv = st->inv_nu;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    static_assert(RU <= kWave / 8, "eight lanes per row in flight for the block write");
+    const int yb = d & ~7;
+    const bool blk = (d & 7) == 7;                 // this column completes its block
+    const int ju = lane >> 3, jj = lane & 7;       // lane 8u + j writes Y(rb + u, yb + j)
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        const bool okb = blk && ju < RU && rb + ju < r1;
+        const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
+        const double vb = (okb && jj == 7) ? v1[rb + ju] : 0.0;
         double y[RU][KC];
         double dots[2 * RU];
 #pragma unroll
@@ -603,7 +652,7 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[u][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
+                y[u][c] = (ok && k < d) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
 #pragma unroll
@@ -618,6 +667,7 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
             dots[RU + u] = b;
         }
         wave_sum_n<2 * RU>(dots);
+        double xb = 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t r = rb + u;
@@ -625,10 +675,12 @@ __global__ __launch_bounds__(256) void gvec2_kernel(double* __restrict__ Y, int6
                 const double v = v1[r] - dots[u];
                 const double xi = v * inv;
                 v2[r] = v;
-                Y[r * ldy + d] = xi;
+                ys[(int64_t)(d - yb) * m + r] = xi;
                 g[r] = w[r] * xi - dots[RU + u];
             }
+            if (ju == u) xb = (vb - dots[u]) * inv;     // the same value, in the lanes of row u's block write
         }
+        if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : xb;
     }
 }
 
@@ -651,8 +703,9 @@ template <int KC, int RU, bool NT>
 __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
                                                      const State* __restrict__ st, int d, int rows_per_blk,
                                                      const double* __restrict__ v1, const double* __restrict__ h2,
-                                                     const double* __restrict__ u, double* __restrict__ v2,
-                                                     double* __restrict__ part, int64_t ldp) {
+                                                     const double* __restrict__ u, double* __restrict__ ys,
+                                                     double* __restrict__ v2, double* __restrict__ part,
+                                                     int64_t ldp) {
     if (st->stop) return;
     constexpr int KW = kWave * KC;
     __shared__ double hs[KW];
@@ -665,6 +718,10 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
     __syncthreads();
     const double inv = st->inv_nu;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    static_assert(RU <= kWave / 8, "eight lanes per row in flight for the block write");
+    const int yb = d & ~7;
+    const bool blk = (d & 7) == 7;                 // this column completes its block
+    const int ju = lane >> 3, jj = lane & 7;       // lane 8u + j writes Y(rb + u, yb + j)
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     double acc[KC];
@@ -672,6 +729,8 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
     for (int c = 0; c < KC; ++c) acc[c] = 0.0;
     double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        const bool okb = blk && ju < RU && rb + ju < r1;
+        const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
         double y[RU][KC];
         double vv[RU], ur[RU], dot[RU];
 #pragma unroll
@@ -684,7 +743,7 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                y[q][c] = (ok && k < d) ? ld_y<NT>(Y + r * ldy + k) : 0.0;
+                y[q][c] = (ok && k < d) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
 #pragma unroll
@@ -695,16 +754,19 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
                 acc[c] = fma(y[q][c], ur[q], acc[c]);
             }
         wave_sum_n<RU>(dot);
+        double xb = 0.0;
 #pragma unroll
         for (int q = 0; q < RU; ++q) {
             const int64_t r = rb + q;
+            const double v = vv[q] - dot[q];
             if (lane == q && r < r1) {
-                const double v = vv[q] - dot[q];
                 v2[r] = v;
-                Y[r * ldy + d] = v * inv;
+                ys[(int64_t)(d - yb) * m + r] = v * inv;
                 nacc = fma(vv[q], ur[q], nacc);
             }
+            if (ju == q) xb = v * inv;
         }
+        if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : xb;
     }
     const double s = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = s;
@@ -728,14 +790,6 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 // The column xi itself is written by the next step's first pass, which reads
 // Y anyway; so each step reads Y once instead of twice.
 // ---------------------------------------------------------------------------
-
-// Deferred columns are staged.  Writing one column of row-major Y costs a
-// partial cache-line write per row (measured: a quarter of the pass's time at
-// m = 2^20), so column c goes to slot c % 8 of ys (m x 8, column-major,
-// contiguous per slot) and reaches Y when its block of 8 columns is complete,
-// as one 64-byte segment per row.  Columns below 8 floor(c / 8) are in Y;
-// columns [8 floor(c / 8), c) only in ys.  ycol copies the staged columns into
-// Y wherever Y must be complete (before an exact refresh, after the loop).
 
 // cgs1_lag: first forms this row's entry of the deferred column d-1,
 //   Y(i, d-1) = (v1p_i - Y(i, 0:d-1) h2p) / nu_prev,
@@ -796,8 +850,7 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                const double* src = k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
-                y[u][c] = (ok && k < dl) ? ld_y<NT>(src) : 0.0;
+                y[u][c] = (ok && k < dl) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
 #pragma unroll
@@ -938,8 +991,7 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 const int k = lane + kWave * c;
-                const double* src = k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
-                y[u][c] = (ok && k < col) ? ld_y<NT>(src) : 0.0;
+                y[u][c] = (ok && k < col) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
             }
         }
         double dot[RU];
