@@ -133,7 +133,13 @@ template <> struct Raw4<f16_t> : Raw4Half<f16_t> {
 };
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
-constexpr int kProjCols = 256, kProjGroup = 4;    // columns per workgroup; k-steps per load group
+constexpr int kProjCols = 256;      // columns per workgroup
+// k-steps per load group: the register budget of two waves per SIMD (measured
+// on MI355X: one wave per SIMD left the matrix cores idle most of the time)
+template <typename Tv, int MT> constexpr int proj_group() {
+    return (sizeof(Tv) == 8 && MT == 4) ? 1 : ((sizeof(Tv) == 8 || MT == 4) ? 2 : 4);
+}
+constexpr int kProjStepMax = 16;    // the largest 4 * proj_group
 
 template <typename Tv, int MT>
 __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m, int d,
@@ -152,7 +158,8 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict
     for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[t][e] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
-    // two register buffers of kProjGroup k-steps, alternated by an unrolled loop
+    // two register buffers of G k-steps: the next group loads while the current one is multiplied
+    constexpr int kProjGroup = proj_group<Tv, MT>();
     double a0[kProjGroup][MT], a1[kProjGroup][MT];
     Raw4<Tv> b0[kProjGroup], b1[kProjGroup];
     auto load = [&](double (&a)[kProjGroup][MT], Raw4<Tv> (&b)[kProjGroup], int64_t k0) {
@@ -181,13 +188,16 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict
                     acc[t][e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][t], be, acc[t][e], 0, 0, 0);
             }
     };
+    // Two groups per iteration and a single exit (an exit between the two halves
+    // made the compiler keep two sets of accumulators: 1 wave per SIMD).  Loads
+    // past the end of the chunk give zeros, so an odd group count costs one
+    // group of products with zeros.
     constexpr int kStep = 4 * kProjGroup;
     load(a0, b0, kb);
     for (int64_t k0 = kb; k0 < ke; k0 += 2 * kStep) {
-        if (k0 + kStep < ke) load(a1, b1, k0 + kStep);
+        load(a1, b1, k0 + kStep);
         mult(a0, b0);
-        if (k0 + kStep >= ke) break;
-        if (k0 + 2 * kStep < ke) load(a0, b0, k0 + 2 * kStep);
+        load(a0, b0, k0 + 2 * kStep);
         mult(a1, b1);
     }
     double* out = part ? part + (int64_t)blockIdx.z * d * N : C;
@@ -211,7 +221,7 @@ hipError_t proj_mfma(const double* Y, int64_t ldy, int64_t m, int d, const Tv* V
     int64_t splits = 1;
     while (ctiles * rtiles * splits < 1024 && m / (splits * 2) >= 1024 && (size_t)(splits * 2) * d * N <= part_elems)
         splits *= 2;
-    const int64_t kchunk = cdv(cdv(m, splits), 4 * kProjGroup) * 4 * kProjGroup;
+    const int64_t kchunk = cdv(cdv(m, splits), kProjStepMax) * kProjStepMax;
     splits = std::max<int64_t>(1, cdv(m, kchunk));
     const int vec_ok = (ldv % 4 == 0) && (reinterpret_cast<uintptr_t>(V) % (4 * sizeof(Tv)) == 0);
     const dim3 grid((unsigned)ctiles, (unsigned)rtiles, (unsigned)splits);
