@@ -6,7 +6,10 @@
 //
 // Tiling: 128 x 128 output tile per workgroup (4 waves, 64 x 64 each, i.e.
 // 4 x 4 MFMA tiles of 16 x 16), k staged through LDS 16 deep with the next
-// chunk's loads in flight while the current one is multiplied.  MFMA operand
+// chunk's loads in flight while the current one is multiplied.  Two waves per
+// SIMD: the launch bound keeps the kernel within 256 registers (the
+// accumulators then live in the unified VGPR file); at one wave per SIMD the
+// matrix cores idled during every chunk's LDS phase.  MFMA operand
 // layout (16x16x4, wave64): lane l supplies A(l % 16, l / 16) and
 // B(l / 16, l % 16); accumulator register r of lane l holds C(4 r + l / 16,
 // l % 16).  With `splits` > 1 the k range is divided over blockIdx.z and each
@@ -25,7 +28,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kGM = 128, kGN = 128, kGK = 16;
 
 template <bool TA, bool TB, typename TAe, typename TBe>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                         const TAe* __restrict__ A, int64_t lda,
                                                         const TBe* __restrict__ B, int64_t ldb, double beta,
                                                         double* __restrict__ C, int64_t ldc, int64_t kchunk,
