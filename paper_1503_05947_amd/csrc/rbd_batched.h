@@ -179,6 +179,7 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
     __shared__ int s_item, s_nf;
     __shared__ int flist[kWave * kCPL];
     __shared__ double red[kWave * kCPL * (TPB / kWave + 1)];
+    __shared__ double tq[(kBatchMaxD + 1) * kRG];     // T(0:d+1, queued group), k-major
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
 
     for (;;) {
@@ -314,13 +315,14 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
                     double r2[kRG];
 #pragma unroll
                     for (int g = 0; g < kRG; ++g) r2[g] = 0.0;
+                    // the group's columns of T(0:d+1, :) into LDS once (every row reads all of them)
+                    for (int e = tid; e < (d + 1) * kRG; e += TPB)
+                        tq[e] = Tb[(int64_t)(e / kRG) * n + flist[min(q0 + e % kRG, nq - 1)]];
+                    __syncthreads();
                     for (int i = tid; i < m; i += TPB) {
                         double acc[kRG];
 #pragma unroll
                         for (int g = 0; g < kRG; ++g) acc[g] = 0.0;
-                        int cols[kRG];
-#pragma unroll
-                        for (int g = 0; g < kRG; ++g) cols[g] = flist[min(q0 + g, nq - 1)];
                         auto part_sum = [&](const double* __restrict__ Yp, int k0, int k1) {
                             int k = k0;
                             for (; k + 4 <= k1; k += 4) {
@@ -330,13 +332,12 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
 #pragma unroll
                                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                                    for (int g = 0; g < kRG; ++g)
-                                        acc[g] = fma(y[u], Tb[(int64_t)(k + u) * n + cols[g]], acc[g]);
+                                    for (int g = 0; g < kRG; ++g) acc[g] = fma(y[u], tq[(k + u) * kRG + g], acc[g]);
                             }
                             for (; k < k1; ++k) {
                                 const double y = Yp[(int64_t)k * m + i];
 #pragma unroll
-                                for (int g = 0; g < kRG; ++g) acc[g] = fma(y, Tb[(int64_t)k * n + cols[g]], acc[g]);
+                                for (int g = 0; g < kRG; ++g) acc[g] = fma(y, tq[k * kRG + g], acc[g]);
                             }
                         };
                         part_sum(ylds, 0, min(d + 1, KL));
