@@ -483,7 +483,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
         if (d > 0) {
-            mv_kernel<<<(unsigned)cdiv(d, 256), 256, 0, s>>>(st, Mw, ldp, d, h2, mh);
+            mv_kernel<<<(unsigned)cdiv(d, 4), 256, 0, s>>>(st, Mw, ldp, d, h2, mh);
             RBD_LAUNCH_CHECK();
         }
         nuw_kernel<<<1, 256, 0, s>>>(st, h2, avec, mh, d, hw, Mw, ldp);
@@ -664,7 +664,7 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
         launch_sum_rows(st, part, ldp, P.cg_S, P.cg_group, d + 1, l2, yu, 0, s);
         RBD_LAUNCH_CHECK();
         if (d > 0) {
-            mv_kernel<<<(unsigned)cdiv(d, 256), 256, 0, s>>>(st, Ma, ldp, d, h2, mh);
+            mv_kernel<<<(unsigned)cdiv(d, 4), 256, 0, s>>>(st, Ma, ldp, d, h2, mh);
             RBD_LAUNCH_CHECK();
         }
         nuw_kernel<<<1, 256, 0, s>>>(st, h2, yu, mh, d, hw, Ma, ldp);

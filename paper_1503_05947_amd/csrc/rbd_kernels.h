@@ -555,16 +555,20 @@ __global__ __launch_bounds__(256) void cgs1w_kernel(const double* __restrict__ x
     }
 }
 
-// mv: Mh = M(0:d, 0:d) h2 (M symmetric, so column reads: coalesced)
+// mv: Mh = M(0:d, 0:d) h2.  M is symmetric, so output k is the dot of row k
+// (contiguous) with h2: one wave per output, lanes along the row.
 __global__ __launch_bounds__(256) void mv_kernel(const State* __restrict__ st, const double* __restrict__ M,
                                                   int64_t ldm, int d, const double* __restrict__ h2,
                                                   double* __restrict__ Mh) {
     if (st->stop) return;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d) return;
+    const int lane = threadIdx.x % kWave;
+    const int k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (k >= d) return;                            // whole waves leave together
+    const double* row = M + (int64_t)k * ldm;
     double s = 0.0;
-    for (int j = 0; j < d; ++j) s = fma(M[(int64_t)j * ldm + k], h2[j], s);
-    Mh[k] = s;
+    for (int j = lane; j < d; j += kWave) s = fma(row[j], h2[j], s);
+    s = wave_sum(s);
+    if (lane == 0) Mh[k] = s;
 }
 
 // nuw: nu, the break test, hw, ||xi||_A^2, and the new row / column of M.
