@@ -296,7 +296,8 @@ int rbd_reconstruct(const double* Y, int64_t ldy, int64_t m, int32_t d, const do
  *   X       m x n, ld ldx, storage xt (the matrix that was fitted)
  *   G       m x n, ld ldg, FP64 or FP32 (the cotangent of Z)
  *   Y, T    the fit's basis (m x d, ld ldy) and coefficients (d x n, ld ldt)
- *   pivots  d int64 (device), the fit's pivots (distinct)
+ *   pivots  d int64 (device), the fit's pivots (distinct, in [0, n); an entry
+ *           outside [0, n) contributes nothing to dX)
  *   dX      m x n FP64 output, ld lddx (overwritten)
  *   workspace  rbd_reconstruct_backward_workspace_size() bytes, 256-aligned
  * 1 <= d <= min(m, n, RBD_MAX_D).  Returns RBD_OK, RBD_EINVAL, RBD_EWORKSPACE

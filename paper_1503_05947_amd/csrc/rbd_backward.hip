@@ -45,31 +45,56 @@ __global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int
     }
 }
 
-// The same inverse for d <= kRinvLds in one workgroup: Rinv is held in LDS and
-// its rows are formed bottom-up, row i for every column j > i at once
-// (thread j; the sum over k runs in the same ascending order as rinv_kernel,
-// so both give identical results); row i of R is staged in LDS first.
-constexpr int kRinvLds = 128;
-__global__ __launch_bounds__(kRinvLds) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
-                                                            const int64_t* __restrict__ piv, int d,
-                                                            double* __restrict__ Rinv) {
-    extern __shared__ double xs[];           // d x d
-    __shared__ double rrow[kRinvLds];
-    const int j = threadIdx.x;
+// The same inverse for d <= kRinvLds in one workgroup of 8 d threads.  The
+// upper triangles of R and of Rinv are held in LDS, packed by rows (row i
+// holds columns i..d-1 at tri_off(i)); R is gathered from T once.  Rows of
+// Rinv are formed bottom-up, row i for every column j > i at once; the eight
+// threads of column j take every eighth k of the sum and combine their
+// partial sums in a fixed order (lanes 8j..8j+7 of one wave).
+constexpr int kRinvLds = 128, kRinvSub = 8;
+__device__ __forceinline__ int tri_off(int i, int d) { return i * d - i * (i - 1) / 2; }
+__global__ __launch_bounds__(kRinvLds * kRinvSub) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
+                                                                       const int64_t* __restrict__ piv, int d,
+                                                                       double* __restrict__ Rinv) {
+    extern __shared__ double sm[];           // packed R, then packed Rinv: d (d + 1) / 2 each
+    const int tri = d * (d + 1) / 2;
+    double* Rp = sm;
+    double* Xp = sm + tri;
+    const int t = threadIdx.x, j = t / kRinvSub, sub = t % kRinvSub;
     for (int i = 0; i < d; ++i)
-        if (j < d) xs[i * d + j] = (i == j) ? 1.0 / T[(int64_t)j * ldt + piv[j]] : 0.0;
+        for (int k = i + t; k < d; k += blockDim.x) Rp[tri_off(i, d) + k - i] = T[(int64_t)i * ldt + piv[k]];
+    __syncthreads();
+    if (sub == 0 && j < d) Xp[tri_off(j, d)] = 1.0 / Rp[tri_off(j, d)];
     for (int i = d - 2; i >= 0; --i) {
         __syncthreads();                      // row i + 1 of Rinv is complete
-        if (j < d) rrow[j] = T[(int64_t)i * ldt + piv[j]];
-        __syncthreads();
-        if (j > i && j < d) {
-            double sum = 0.0;
-            for (int k = i + 1; k <= j; ++k) sum = fma(rrow[k], xs[k * d + j], sum);
-            xs[i * d + j] = -sum / rrow[i];
-        }
+        const double* ri = Rp + tri_off(i, d) - i;              // ri[k] = R(i, k), k >= i
+        double sum = 0.0;
+        if (j > i && j < d)
+            for (int k = i + 1 + sub; k <= j; k += kRinvSub) sum = fma(ri[k], Xp[tri_off(k, d) + j - k], sum);
+        // lanes 8j .. 8j + 7 (every lane of the wave takes part)
+        sum += __shfl_xor(sum, 1);
+        sum += __shfl_xor(sum, 2);
+        sum += __shfl_xor(sum, 4);
+        if (sub == 0 && j > i && j < d) Xp[tri_off(i, d) + j - i] = -sum / ri[i];
     }
     __syncthreads();
-    for (int e = j; e < d * d; e += blockDim.x) Rinv[e] = xs[e];
+    for (int e = t; e < d * d; e += blockDim.x) {
+        const int r = e / d, c = e % d;
+        Rinv[e] = c >= r ? Xp[tri_off(r, d) + c - r] : 0.0;
+    }
+}
+
+// dX(:, piv[k]) += Abar(:, k)   (pivots are distinct; one outside [0, n) is skipped)
+__global__ void scatter_add_cols_kernel(const double* __restrict__ Abar, int64_t m, int d,
+                                        const int64_t* __restrict__ piv, int64_t n, double* __restrict__ dX,
+                                        int64_t lddx) {
+    const int64_t tot = m * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / d;
+        const int k = (int)(e % d);
+        const int64_t c = piv[k];
+        if (c >= 0 && c < n) dX[i * lddx + c] += Abar[e];
+    }
 }
 
 // S = tril(M) + tril(M, -1)'
@@ -78,17 +103,6 @@ __global__ void copyltu_kernel(const double* __restrict__ Mm, int d, double* __r
     if (e >= (int64_t)d * d) return;
     const int i = (int)(e / d), j = (int)(e % d);
     S[e] = Mm[(int64_t)max(i, j) * d + min(i, j)];
-}
-
-// dX(:, piv[k]) += Abar(:, k)   (pivots are distinct)
-__global__ void scatter_add_cols_kernel(const double* __restrict__ Abar, int64_t m, int d,
-                                        const int64_t* __restrict__ piv, double* __restrict__ dX, int64_t lddx) {
-    const int64_t tot = m * d;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / d;
-        const int k = (int)(e % d);
-        dX[i * lddx + piv[k]] += Abar[e];
-    }
 }
 
 struct BwdPlan {
@@ -140,16 +154,16 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
     // Abar = Ybar R^{-T};  dX(:, P) += Abar
     if (d <= kRinvLds) {
-        const size_t lds = sizeof(double) * (size_t)d * d;
+        const size_t lds = sizeof(double) * (size_t)d * (d + 1);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        rinv_lds_kernel<<<1, kRinvLds, lds, s>>>(T, ldt, piv, d, Rinv);
+        rinv_lds_kernel<<<1, kRinvLds * kRinvSub, lds, s>>>(T, ldt, piv, d, Rinv);
     } else {
         rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, Rinv);
     }
     ok(hipGetLastError());
     ok(gemm<false, true, double, double>(m, d, d, 1.0, Ybar, d, Rinv, d, 0.0, Abar, d, nullptr, 0, s));
-    scatter_add_cols_kernel<<<(unsigned)std::min<int64_t>(4096, cd(m * d, 256)), 256, 0, s>>>(Abar, m, d, piv, dX,
+    scatter_add_cols_kernel<<<(unsigned)std::min<int64_t>(4096, cd(m * d, 256)), 256, 0, s>>>(Abar, m, d, piv, n, dX,
                                                                                               lddx);
     ok(hipGetLastError());
     return e == hipSuccess ? RBD_OK : RBD_EDEVICE;

@@ -120,14 +120,24 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
             }
 }
 
-// C = alpha * sum_{s < splits} part[s] + beta * C (fixed order over s).
+// C = alpha * sum_{s < splits} part[s] + beta * C in a fixed order: eight
+// interleaved chains (split q goes to chain q % 8, eight loads in flight per
+// thread), then the chains in order.
 static __global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, int64_t N, int splits, double alpha,
                                                               const double* __restrict__ part, double beta,
                                                               double* __restrict__ C, int64_t ldc) {
     const int64_t tot = M * N;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        double g[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 8 <= splits; q += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) g[u] += part[(int64_t)(q + u) * tot + e];
+        }
+        for (int u = 0; q < splits; ++q, ++u) g[u] += part[(int64_t)q * tot + e];
         double s = 0.0;
-        for (int q = 0; q < splits; ++q) s += part[(int64_t)q * tot + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += g[u];
         const int64_t i = e / N, j = e % N;
         const double prev = beta != 0.0 ? C[i * ldc + j] : 0.0;
         C[i * ldc + j] = alpha * s + beta * prev;
