@@ -45,43 +45,38 @@ __global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int
     }
 }
 
-// The same inverse for d <= kRinvLds in one workgroup of 8 d threads.  The
-// upper triangles of R and of Rinv are held in LDS, packed by rows (row i
-// holds columns i..d-1 at tri_off(i)); R is gathered from T once.  Rows of
-// Rinv are formed bottom-up, row i for every column j > i at once; the eight
-// threads of column j take every eighth k of the sum and combine their
-// partial sums in a fixed order (lanes 8j..8j+7 of one wave).
-constexpr int kRinvLds = 128, kRinvSub = 8;
+// The same inverse for d <= kRinvLds: one wave per column j of Rinv, solving
+// R x = e_j by back substitution.  Lane l keeps x(l) and x(l + 64) in
+// registers; each step i is one wave sum of R(i, k) x(k) over k in (i, j].
+// R's upper triangle is staged in LDS once per workgroup, packed by rows
+// (row i holds columns i..d-1 at tri_off(i)).
+constexpr int kRinvLds = 128;
 __device__ __forceinline__ int tri_off(int i, int d) { return i * d - i * (i - 1) / 2; }
-__global__ __launch_bounds__(kRinvLds * kRinvSub) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
-                                                                       const int64_t* __restrict__ piv, int d,
-                                                                       double* __restrict__ Rinv) {
-    extern __shared__ double sm[];           // packed R, then packed Rinv: d (d + 1) / 2 each
-    const int tri = d * (d + 1) / 2;
-    double* Rp = sm;
-    double* Xp = sm + tri;
-    const int t = threadIdx.x, j = t / kRinvSub, sub = t % kRinvSub;
+__global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
+                                                       const int64_t* __restrict__ piv, int d,
+                                                       double* __restrict__ Rinv) {
+    extern __shared__ double Rp[];           // packed R: d (d + 1) / 2
     for (int i = 0; i < d; ++i)
-        for (int k = i + t; k < d; k += blockDim.x) Rp[tri_off(i, d) + k - i] = T[(int64_t)i * ldt + piv[k]];
+        for (int k = i + threadIdx.x; k < d; k += blockDim.x) Rp[tri_off(i, d) + k - i] = T[(int64_t)i * ldt + piv[k]];
     __syncthreads();
-    if (sub == 0 && j < d) Xp[tri_off(j, d)] = 1.0 / Rp[tri_off(j, d)];
-    for (int i = d - 2; i >= 0; --i) {
-        __syncthreads();                      // row i + 1 of Rinv is complete
-        const double* ri = Rp + tri_off(i, d) - i;              // ri[k] = R(i, k), k >= i
+    const int lane = threadIdx.x % kWave;
+    const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (j >= d) return;                      // whole waves leave together
+    const int k0 = lane, k1 = lane + kWave;
+    double x0 = (k0 == j) ? 1.0 / Rp[tri_off(j, d)] : 0.0;
+    double x1 = (k1 == j) ? 1.0 / Rp[tri_off(j, d)] : 0.0;
+    for (int i = j - 1; i >= 0; --i) {
+        const double* ri = Rp + tri_off(i, d) - i;             // ri[k] = R(i, k), k >= i
         double sum = 0.0;
-        if (j > i && j < d)
-            for (int k = i + 1 + sub; k <= j; k += kRinvSub) sum = fma(ri[k], Xp[tri_off(k, d) + j - k], sum);
-        // lanes 8j .. 8j + 7 (every lane of the wave takes part)
-        sum += __shfl_xor(sum, 1);
-        sum += __shfl_xor(sum, 2);
-        sum += __shfl_xor(sum, 4);
-        if (sub == 0 && j > i && j < d) Xp[tri_off(i, d) + j - i] = -sum / ri[i];
+        if (k0 > i && k0 <= j) sum = ri[k0] * x0;
+        if (k1 > i && k1 <= j) sum = fma(ri[k1], x1, sum);
+        sum = wave_sum(sum);
+        const double v = -sum / ri[i];
+        if (k0 == i) x0 = v;
+        if (k1 == i) x1 = v;
     }
-    __syncthreads();
-    for (int e = t; e < d * d; e += blockDim.x) {
-        const int r = e / d, c = e % d;
-        Rinv[e] = c >= r ? Xp[tri_off(r, d) + c - r] : 0.0;
-    }
+    if (k0 < d) Rinv[(int64_t)k0 * d + j] = x0;
+    if (k1 < d) Rinv[(int64_t)k1 * d + j] = x1;
 }
 
 // dX(:, piv[k]) += Abar(:, k)   (pivots are distinct; one outside [0, n) is skipped)
@@ -154,10 +149,10 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
     // Abar = Ybar R^{-T};  dX(:, P) += Abar
     if (d <= kRinvLds) {
-        const size_t lds = sizeof(double) * (size_t)d * (d + 1);
+        const size_t lds = sizeof(double) * (size_t)d * (d + 1) / 2;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        rinv_lds_kernel<<<1, kRinvLds * kRinvSub, lds, s>>>(T, ldt, piv, d, Rinv);
+        rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(T, ldt, piv, d, Rinv);
     } else {
         rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, Rinv);
     }
