@@ -47,31 +47,39 @@ __global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int
 
 // The same inverse for d <= kRinvLds: one wave per column j of Rinv, solving
 // R x = e_j by back substitution.  Lane l keeps x(l) and x(l + 64) in
-// registers; each step i is one wave sum of R(i, k) x(k) over k in (i, j].
-// R's upper triangle is staged in LDS once per workgroup, packed by rows
-// (row i holds columns i..d-1 at tri_off(i)).
+// registers; each step i is one wave sum of R(i, k) x(k) over k in (i, j],
+// times 1 / R(i, i).  R's upper triangle is staged in LDS once per workgroup,
+// packed by rows (row i holds columns i..d-1 at tri_off(i)), with the
+// reciprocals of its diagonal after it.
 constexpr int kRinvLds = 128;
 __device__ __forceinline__ int tri_off(int i, int d) { return i * d - i * (i - 1) / 2; }
 __global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
                                                        const int64_t* __restrict__ piv, int d,
                                                        double* __restrict__ Rinv) {
-    extern __shared__ double Rp[];           // packed R: d (d + 1) / 2
-    for (int i = 0; i < d; ++i)
-        for (int k = i + threadIdx.x; k < d; k += blockDim.x) Rp[tri_off(i, d) + k - i] = T[(int64_t)i * ldt + piv[k]];
+    extern __shared__ double Rp[];           // packed R: d (d + 1) / 2, then 1 / R(i, i): d
+    double* rd = Rp + d * (d + 1) / 2;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {      // independent loads, all in flight
+        const int i = e / d, k = e % d;
+        if (k >= i) {
+            const double v = T[(int64_t)i * ldt + piv[k]];
+            Rp[tri_off(i, d) + k - i] = v;
+            if (k == i) rd[i] = 1.0 / v;
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x % kWave;
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= d) return;                      // whole waves leave together
     const int k0 = lane, k1 = lane + kWave;
-    double x0 = (k0 == j) ? 1.0 / Rp[tri_off(j, d)] : 0.0;
-    double x1 = (k1 == j) ? 1.0 / Rp[tri_off(j, d)] : 0.0;
+    double x0 = (k0 == j) ? rd[j] : 0.0;
+    double x1 = (k1 == j) ? rd[j] : 0.0;
     for (int i = j - 1; i >= 0; --i) {
         const double* ri = Rp + tri_off(i, d) - i;             // ri[k] = R(i, k), k >= i
         double sum = 0.0;
         if (k0 > i && k0 <= j) sum = ri[k0] * x0;
         if (k1 > i && k1 <= j) sum = fma(ri[k1], x1, sum);
         sum = wave_sum(sum);
-        const double v = -sum / ri[i];
+        const double v = -sum * rd[i];
         if (k0 == i) x0 = v;
         if (k1 == i) x1 = v;
     }
@@ -149,7 +157,7 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
     // Abar = Ybar R^{-T};  dX(:, P) += Abar
     if (d <= kRinvLds) {
-        const size_t lds = sizeof(double) * (size_t)d * (d + 1) / 2;
+        const size_t lds = sizeof(double) * ((size_t)d * (d + 1) / 2 + d);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(T, ldt, piv, d, Rinv);
