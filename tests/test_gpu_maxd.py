@@ -62,3 +62,20 @@ def test_spd_at_max_d(gauss):
     ref = oracle.rbd_fit(vals, 0.0, D, A=A)
     msgs = compare_fit(dev, ref, vals, gap=1e-6, norms=lambda R: _norms_A(R, A))
     assert msgs == [], "; ".join(msgs)
+
+
+@pytest.mark.parametrize("m,n,d_max", [(100, 250_000, 24), (2_000_000, 8, 8)])
+def test_extreme_shapes(m, n, d_max):
+    """Very wide (many column blocks in the update and argmax, a long refresh
+    queue) and very tall and skinny (two 16-byte vectors per row of X)."""
+    import paper_1503_05947_amd as rbd
+    g = synth.rng(98, m % 1000, n % 1000)
+    r = min(m, n, 12)
+    X = (g.standard_normal((m, r)) * (10.0 ** -np.arange(r) / 2)) @ g.standard_normal((r, n)) \
+        + 1e-6 * g.standard_normal((m, n))
+    stored, vals = synth.quantize(X, "f32")
+    print(f"[gpu] extreme shape {m}x{n} d_max={d_max}", flush=True)
+    dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=d_max))
+    ref = oracle.rbd_fit(vals, 0.0, d_max)
+    msgs = compare_fit(dev, ref, vals, gap=1e-6)
+    assert msgs == [], "; ".join(msgs)
