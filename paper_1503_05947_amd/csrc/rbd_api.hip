@@ -129,7 +129,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->o_M = take(8 * (size_t)std::max(P->D, 1) * std::max(P->D, 1));    // Y'WY (diagonal A)
     P->o_mh = take(8 * ((size_t)RBD_MAX_D + 1));
     P->o_hw = take(8 * (size_t)RBD_MAX_D);
-    P->o_ys = take(8 * 8 * (size_t)m);      // staged deferred columns (A = I), m x 8 column-major
+    P->o_ys = take(8 * 8 * (size_t)m);      // staged basis columns (every path), m x 8 column-major
     // scan partials (two rows of n per slab with an A-norm); Gram-Schmidt partials.  The
     // lagged path (rows of n) and the SPD path (rows of 2n) add up to ceil(D / kTcorr)
     // correction rows after the scan's slabs.
