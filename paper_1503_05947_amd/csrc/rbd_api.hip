@@ -338,12 +338,17 @@ void launch_ys_flush(const FitPlan& P, double* Y, const State* st, int cols, con
     ys_flush_kernel<FINAL><<<g, 256, 0, s>>>(Y, P.d_max, P.m, st, cols, ys);
 }
 
-// out[c] = sum_r part[r * ldp + c] for c < len in two fixed-order levels (rows in
-// groups of `per`, then the group sums), through `l2` (ceil(rows/per) x ldp).
+// out[c] = sum_r part[r * ldp + c] for c < len in a fixed order: rows in groups
+// of `per`, then the group sums, through `l2` (ceil(rows/per) x ldp); with at
+// most 256 rows, one sequential level.
 void launch_sum_rows(const State* st, const double* part, int64_t ldp, int rows, int per, int64_t len, double* l2,
                      double* out, int64_t ldo_final, hipStream_t s) {
-    const int groups = (int)cdiv(rows, per);
     const unsigned gx = (unsigned)cdiv(len, 256);
+    if (rows <= 256) {          // few rows: one level, one launch
+        reduce_rows_kernel<<<dim3(gx, 1), 256, 0, s>>>(st, part, ldp, rows, rows, len, out, ldo_final);
+        return;
+    }
+    const int groups = (int)cdiv(rows, per);
     reduce_rows_kernel<<<dim3(gx, groups), 256, 0, s>>>(st, part, ldp, rows, per, len, l2, ldp);
     reduce_rows_kernel<<<dim3(gx, 1), 256, 0, s>>>(st, l2, ldp, groups, groups, len, out, ldo_final);
 }
@@ -422,14 +427,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS1, s);
         prof_begin(RBD_PHASE_CGS2, s);
-        nu_lag_kernel<<<1, 256, 0, s>>>(st, h2s[c], d);
-        RBD_LAUNCH_CHECK();
         const int kp = d > 0 ? (int)cdiv(d, kTcorr) : 0;
-        if (kp) {
-            tcorr_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)kp), 256, 0, s>>>(
-                st, h2s[c], d, T, P.n, P.n, part + (int64_t)P.sc_S * P.n);
-            RBD_LAUNCH_CHECK();
-        }
+        nu_tcorr_kernel<<<dim3(kp ? (unsigned)cdiv(P.n, 256) : 1u, (unsigned)std::max(kp, 1)), 256, 0, s>>>(
+            st, h2s[c], d, T, P.n, P.n, part + (int64_t)P.sc_S * P.n);
+        RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_CGS2, s);
         prof_begin(RBD_PHASE_XSCAN, s);
         launch_xscan<Tx, kScanDot>(P, X, ldx, v1s[c], st, Y, -1, part, vec_ok, nt, s);

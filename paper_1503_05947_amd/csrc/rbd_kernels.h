@@ -9,9 +9,9 @@
 //   cgs1_lag      writes the previous step's basis column, then
 //                 v1 = x_p - Y h1 with h1 = T(0:d, p) (h1 = Y' x_p is already a
 //                 column of T), with per-block partials of h2 = Y' v1, ||v1||^2
-//   reduce        h2 and ||v1||^2 = fixed-order sums (two small launches)
-//   nu_lag        nu^2 = ||v1||^2 - ||h2||^2, step 2.2's break test
-//   tcorr         correction rows -h2' T(0:d, :) / nu
+//   reduce        h2 and ||v1||^2 = fixed-order sums (one or two small launches)
+//   nu_tcorr      nu^2 = ||v1||^2 - ||h2||^2, step 2.2's break test, and the
+//                 correction rows -h2' T(0:d, :) / nu
 //   xscan         partial (v1 / nu)' X per row slab
 //   reduce        slab partials (and correction rows) into group partials
 //   update        T(d, :); e_j^2 -= T(d, j)^2; queue columns for an exact
@@ -919,22 +919,42 @@ __global__ __launch_bounds__(256) void nu_lag_kernel(State* __restrict__ st, con
     }
 }
 
-// tcorr: the correction rows -h2' T(0:d, :) / nu, one partial row per chunk of
-// kTcorr rows of T (grid: column blocks x chunks); summed after the scan's
-// slab partials in a fixed order.
+// Correction rows -h2' T(0:d, :) / nu of the lagged step, one partial row per
+// chunk of kTcorr rows of T (grid: column blocks x chunks); summed after the
+// scan's slab partials in a fixed order.
 constexpr int kTcorr = 32;
-__global__ __launch_bounds__(256) void tcorr_kernel(const State* __restrict__ st, const double* __restrict__ h2,
-                                                     int d, const double* __restrict__ T, int64_t ldt, int64_t n,
-                                                     double* __restrict__ out) {
+
+// nu_tcorr: nu and the break test with the correction rows, in one launch.
+// Every block forms nu from h2 in the same fixed order (so all agree with each
+// other and with nu_lag_kernel), block (0, 0) records nu / the break test, and
+// the blocks write the correction rows of their column block and chunk.
+__global__ __launch_bounds__(256) void nu_tcorr_kernel(State* __restrict__ st, const double* __restrict__ h2, int d,
+                                                        const double* __restrict__ T, int64_t ldt, int64_t n,
+                                                        double* __restrict__ out) {
     if (st->stop) return;
+    __shared__ double sred[4];
+    double q = 0.0;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) q = fma(h2[k], h2[k], q);
+    q = block_sum(q, sred);
+    const double s2 = h2[d] - q;
+    const double nu = s2 > 0.0 ? sqrt(s2) : 0.0;
+    const bool brk = nu < st->tau || nu == 0.0;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        st->nu = nu;
+        if (brk) st->stop = RBD_STOP_BREAK;
+        else st->inv_nu = 1.0 / nu;
+    }
+    if (brk || d == 0) return;
+    const double inv = 1.0 / nu;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int k0 = blockIdx.y * kTcorr, k1 = min(d, k0 + kTcorr);
     double c = 0.0;
 #pragma unroll 8
     for (int k = k0; k < k1; ++k) c = fma(h2[k], T[(int64_t)k * ldt + j], c);
-    out[(int64_t)blockIdx.y * n + j] = -c * st->inv_nu;
+    out[(int64_t)blockIdx.y * n + j] = -c * inv;
 }
+
 
 // tcorr2: rows of 2n for the two-vector scan: zeros in the first n, then
 // -hw' T(k0:k1, :) for a chunk of kTcorr rows of T (hw already divided by nu).
