@@ -18,6 +18,7 @@
 
 #include "../../include/rbd.h"
 #include "rbd_kernels.h"
+#include "rbd_proj.h"
 
 namespace {
 
@@ -738,29 +739,33 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
 
 // ---------------------------------------------------------------------------
 struct ProjPlan {
-    int S = 1, rows = 0;
+    size_t part_elems = 0;      // split-k partials of C = Y'V
     int rc_rows = 0, rc_S = 0, rc_grid = 0;
-    size_t o_part, o_rpart, total;
+    int rs_per = 0, rs_groups = 0;  // residual partials summed in groups of rs_per slabs, then the groups
+    size_t o_part, o_rpart, o_rgroup, total;
 };
 
 bool make_proj_plan(int64_t m, int32_t d, int64_t k, ProjPlan* P) {
     if (m < 1 || d < 1 || k < 1 || d > RBD_MAX_D || k >= (int64_t)INT32_MAX) return false;
-    P->S = (int)std::max<int64_t>(1, std::min<int64_t>(32, cdiv(m, 8192)));
-    P->rows = (int)cdiv(m, P->S);
-    P->rows = (int)(cdiv(P->rows, 16) * 16);
-    P->S = (int)cdiv(m, P->rows);
-    int64_t rrow = std::max<int64_t>(128, cdiv(cdiv(m, 64), 128) * 128);
+    // room for the k-splits that bring the product to about 1024 workgroups
+    P->part_elems = (size_t)std::min<int64_t>((int64_t)kPartElems, std::min<int64_t>(1024, cdiv(m, 1024)) * d * k);
+    // residual norms: row slabs of a multiple of 128 rows, enough for about 4096 (tile, slab) items
+    const int64_t slabs = std::max<int64_t>(32, cdiv(4096, cdiv(k, 64)));
+    int64_t rrow = std::min<int64_t>(std::max<int64_t>(128, cdiv(cdiv(m, slabs), 128) * 128), INT32_MAX / 2);
     P->rc_rows = (int)rrow;
     P->rc_S = (int)cdiv(m, rrow);
     P->rc_grid = (int)std::min<int64_t>(2048, cdiv(k, 64) * P->rc_S);
+    P->rs_per = std::min(P->rc_S, 64);
+    P->rs_groups = (int)cdiv(P->rc_S, P->rs_per);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
         o = align_up(o + bytes);
         return at;
     };
-    P->o_part = take(8 * (size_t)P->S * d * k);
+    P->o_part = take(8 * P->part_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * k);
+    P->o_rgroup = take(8 * (size_t)P->rs_groups * k);
     P->total = o;
     return true;
 }
@@ -770,16 +775,23 @@ int project_typed(const ProjPlan& P, const double* Y, int64_t ldy, int64_t m, in
                   int64_t ldv, double* Tv_out, double* err_v, char* ws, hipStream_t s) {
     double* part = reinterpret_cast<double*>(ws + P.o_part);
     double* rpart = reinterpret_cast<double*>(ws + P.o_rpart);
-    const dim3 g((unsigned)cdiv(d, 64), (unsigned)cdiv(k, 64), (unsigned)P.S);
-    gemm_tn_partial_kernel<Tv><<<g, 256, 0, s>>>(Y, ldy, m, d, V, ldv, k, P.rows, part);
-    RBD_LAUNCH_CHECK();
-    const int64_t len = (int64_t)d * k;
-    sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(len, 256)), 256, 0, s>>>(part, P.S, len, Tv_out, 0);
-    RBD_LAUNCH_CHECK();
+    double* rgroup = reinterpret_cast<double*>(ws + P.o_rgroup);
+    // coefficients on the FP64 matrix cores (split-k partials summed in a fixed order)
+    if (proj_mfma<Tv>(Y, ldy, m, d, V, ldv, k, Tv_out, k, part, P.part_elems, s) != hipSuccess) return RBD_EDEVICE;
     resid_mfma_kernel<Tv><<<P.rc_grid, 256, 0, s>>>(V, ldv, m, Y, ldy, d, Tv_out, k, nullptr, nullptr, (int)k, P.rc_rows,
                                                P.rc_S, rpart, k, nullptr);
     RBD_LAUNCH_CHECK();
-    sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(k, 256)), 256, 0, s>>>(rpart, P.rc_S, k, err_v, 1);
+    // slab partials -> group sums -> norms, every sum in ascending order (two levels keep
+    // each thread's serial chain short when k is small and the slabs are many)
+    const double* rsum = rpart;
+    if (P.rs_groups > 1) {
+        reduce_rows_kernel<<<dim3((unsigned)cdiv(k, 256), (unsigned)P.rs_groups), 256, 0, s>>>(
+            nullptr, rpart, k, P.rc_S, P.rs_per, k, rgroup, k);
+        RBD_LAUNCH_CHECK();
+        rsum = rgroup;
+    }
+    sum_rows_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(k, 256)), 256, 0, s>>>(rsum, P.rs_groups > 1 ? P.rs_groups : P.rc_S,
+                                                                                     k, err_v, 1);
     RBD_LAUNCH_CHECK();
     return RBD_OK;
 }

@@ -1414,64 +1414,8 @@ __global__ void epilogue_kernel(const State* __restrict__ st, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// projection: C = Y' V over row slabs (partials), then a fixed-order sum.
+// fixed-order sums of per-slab partials
 // ---------------------------------------------------------------------------
-template <typename Tv>
-__global__ __launch_bounds__(256) void gemm_tn_partial_kernel(const double* __restrict__ Y, int64_t ldy,
-                                                               int64_t m, int d, const Tv* __restrict__ V,
-                                                               int64_t ldv, int64_t k, int rows_per_slab,
-                                                               double* __restrict__ part) {
-    __shared__ double Ys[16][65];
-    __shared__ double Vs[16][65];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int a0 = blockIdx.x * 64;
-    const int64_t q0 = (int64_t)blockIdx.y * 64;
-    const int s = blockIdx.z;
-    const int64_t rbeg = (int64_t)s * rows_per_slab;
-    const int64_t rend = min(m, rbeg + (int64_t)rows_per_slab);
-    double acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-    for (int64_t row0 = rbeg; row0 < rend; row0 += 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + 256 * q;
-            const int rr = e >> 6, cc = e & 63;
-            const int64_t row = row0 + rr;
-            const int a = a0 + cc;
-            const int64_t qq = q0 + cc;
-            Ys[rr][cc] = (row < rend && a < d) ? Y[row * ldy + a] : 0.0;
-            Vs[rr][cc] = (row < rend && qq < k) ? Ld<Tv>::one(V + row * ldv + qq) : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            double yv[4], vv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) yv[a] = Ys[rr][ty + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) vv[b] = Vs[rr][tx + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = fma(yv[a], vv[b], acc[a][b]);
-        }
-        __syncthreads();
-    }
-    double* out = part + (int64_t)s * d * k;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int aa = a0 + ty + 16 * a;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t qq = q0 + tx + 16 * b;
-            if (aa < d && qq < k) out[(int64_t)aa * k + qq] = acc[a][b];
-        }
-    }
-}
-
 // out[e] = f(sum_{s < S} part[s * len + e]) with f = identity or sqrt.
 __global__ void sum_rows_kernel(const double* __restrict__ part, int S, int64_t len, double* __restrict__ out,
                                 int take_sqrt) {

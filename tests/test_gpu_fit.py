@@ -263,3 +263,23 @@ def test_project_reproduces_fit_columns():
     mask = np.ones(vals.shape[1], bool)
     mask[dev["pivots"]] = False
     assert np.max(np.abs(err[mask] - dev["col_err"][mask])) < 1e-9 * np.linalg.norm(vals, axis=0).max()
+
+
+@pytest.mark.parametrize("m,d,k,vdtype", [(300000, 70, 7, "f16"), (300000, 64, 1, "f32"), (40000, 200, 300, "f32"),
+                                          (131072, 1024, 65, "bf16")])
+def test_project_many_row_splits(m, d, k, vdtype):
+    """Enough rows that the product is split over rows and the residual partials
+    are summed in two levels; ragged d and k, several storage types."""
+    import paper_1503_05947_amd as rbd
+    torch = _torch()
+    print(f"[gpu] project m={m} d={d} k={k} {vdtype}", flush=True)
+    Y = synth.haar(synth.rng(97, m, d), m, d)
+    V64 = synth.rng(98, m, k).standard_normal((m, k))
+    V64[:, : min(k, 3)] += Y[:, :3] @ np.ones((3, min(k, 3)))     # components inside span(Y)
+    Vs, Vv = synth.quantize(V64, vdtype)
+    Tv, err = rbd.project(torch.from_numpy(Y).cuda(), to_device(Vs, vdtype))
+    C, e = oracle.rbd_project(Y, Vv)
+    Tv, err = Tv.cpu().numpy(), err.cpu().numpy()
+    scale = np.linalg.norm(Vv, axis=0)
+    assert np.max(np.linalg.norm(Tv - C, axis=0) / scale) < 1e-12
+    assert np.max(np.abs(err - e) / scale) < 1e-12
