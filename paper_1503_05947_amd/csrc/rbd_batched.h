@@ -73,28 +73,41 @@ __device__ __forceinline__ void col_pass(const Tx* __restrict__ Xb, int m, int n
     bool ok[kCPL];
 #pragma unroll
     for (int c = 0; c < kCPL; ++c) ok[c] = j0 + lane + kWave * c < n;
+    // Loads without branches: a lane past the last column reads column 0 of
+    // the same row and drops the value.  (A load guarded by a branch, with its
+    // conversion in the same branch, waits for its data before the next load
+    // issues.)
+    int off[kCPL];
+#pragma unroll
+    for (int c = 0; c < kCPL; ++c) off[c] = ok[c] ? j0 + lane + kWave * c : 0;
     int i = w;
     for (; i + 3 * NW < m; i += 4 * NW) {
-        double x[4][kCPL];
+        Tx xr[4][kCPL];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const Tx* r = Xb + (int64_t)(i + u * NW) * n + j0 + lane;
+            const Tx* r = Xb + (int64_t)(i + u * NW) * n;
 #pragma unroll
-            for (int c = 0; c < kCPL; ++c) x[u][c] = ok[c] ? L::one(r + kWave * c) : 0.0;
+            for (int c = 0; c < kCPL; ++c) xr[u][c] = r[off[c]];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double wu = SQR ? 0.0 : wts[i + u * NW];
 #pragma unroll
-            for (int c = 0; c < kCPL; ++c) t[c] = SQR ? fma(x[u][c], x[u][c], t[c]) : fma(wu, x[u][c], t[c]);
+            for (int c = 0; c < kCPL; ++c) {
+                const double x = ok[c] ? L::from(xr[u][c]) : 0.0;
+                t[c] = SQR ? fma(x, x, t[c]) : fma(wu, x, t[c]);
+            }
         }
     }
     for (; i < m; i += NW) {
-        const Tx* r0 = Xb + (int64_t)i * n + j0 + lane;
+        const Tx* r0 = Xb + (int64_t)i * n;
         const double w0 = SQR ? 0.0 : wts[i];
+        Tx xr[kCPL];
+#pragma unroll
+        for (int c = 0; c < kCPL; ++c) xr[c] = r0[off[c]];
 #pragma unroll
         for (int c = 0; c < kCPL; ++c) {
-            const double x = ok[c] ? L::one(r0 + kWave * c) : 0.0;
+            const double x = ok[c] ? L::from(xr[c]) : 0.0;
             t[c] = SQR ? fma(x, x, t[c]) : fma(w0, x, t[c]);
         }
     }
@@ -342,10 +355,13 @@ __global__ __launch_bounds__(TPB) void batched_fit_kernel(
                         };
                         part_sum(ylds, 0, min(d + 1, KL));
                         part_sum(Yt, min(d + 1, KL), d + 1);
+                        Tx xr[kRG];      // past the queue's end: a repeat of its first entry, unused
+#pragma unroll
+                        for (int g = 0; g < kRG; ++g) xr[g] = Xb[(int64_t)i * n + flist[q0 + g < nq ? q0 + g : q0]];
 #pragma unroll
                         for (int g = 0; g < kRG; ++g)
                             if (q0 + g < nq) {
-                                const double r = L::one(Xb + (int64_t)i * n + flist[q0 + g]) - acc[g];
+                                const double r = L::from(xr[g]) - acc[g];
                                 r2[g] = fma(r, r, r2[g]);
                             }
                     }

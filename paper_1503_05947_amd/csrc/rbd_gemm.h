@@ -46,9 +46,12 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
         for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
     // the next chunk's operands are loaded into registers while the current
-    // chunk, already in LDS, is multiplied
+    // chunk, already in LDS, is multiplied; they stay in their storage format
+    // until they go to LDS (a conversion right after a guarded load would make
+    // each load wait for its data before the next one issues)
     constexpr int QA = (kGM * kGK) / 256, QB = (kGN * kGK) / 256;
-    double ra[QA], rb[QB];
+    TAe ra[QA];
+    TBe rb[QB];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
             if (TA) { k = e / kGM; i = e % kGM; }     // A stored K x M: rows of A are k
             else { i = e / kGK; k = e % kGK; }        // A stored M x K
             const int64_t gi = row0 + i, gk = k0 + k;
-            ra[q] = (gi < M && gk < ke) ? (TA ? Ld<TAe>::one(A + gk * lda + gi) : Ld<TAe>::one(A + gi * lda + gk)) : 0.0;
+            ra[q] = (gi < M && gk < ke) ? (TA ? A[gk * lda + gi] : A[gi * lda + gk]) : TAe{};
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
@@ -66,7 +69,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
             if (TB) { j = e / kGK; k = e % kGK; }     // B stored N x K
             else { k = e / kGN; j = e % kGN; }        // B stored K x N
             const int64_t gj = col0 + j, gk = k0 + k;
-            rb[q] = (gj < N && gk < ke) ? (TB ? Ld<TBe>::one(B + gj * ldb + gk) : Ld<TBe>::one(B + gk * ldb + gj)) : 0.0;
+            rb[q] = (gj < N && gk < ke) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : TBe{};
         }
     };
     if (kb < ke) load(kb);
@@ -75,14 +78,14 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
             const int e = tid + 256 * q;
-            if (TA) As[e / kGM][e % kGM] = ra[q];
-            else As[e % kGK][e / kGK] = ra[q];
+            if (TA) As[e / kGM][e % kGM] = Ld<TAe>::from(ra[q]);
+            else As[e % kGK][e / kGK] = Ld<TAe>::from(ra[q]);
         }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
             const int e = tid + 256 * q;
-            if (TB) Bs[e % kGK][e / kGK] = rb[q];
-            else Bs[e / kGN][e % kGN] = rb[q];
+            if (TB) Bs[e % kGK][e / kGK] = Ld<TBe>::from(rb[q]);
+            else Bs[e / kGN][e % kGN] = Ld<TBe>::from(rb[q]);
         }
         __syncthreads();
         if (k0 + kGK < ke) load(k0 + kGK);
@@ -144,7 +147,7 @@ static __global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, i
     }
 }
 
-constexpr size_t kPartElems = (size_t)4 << 20;   // split-k partials: 32 MB
+constexpr size_t kPartElems = (size_t)8 << 20;   // split-k partials: 64 MB
 
 // Host side: C = alpha op(A) op(B) + beta C.  The k range is split (partials
 // in `part`, at most part_elems doubles, summed in a fixed order) while the
