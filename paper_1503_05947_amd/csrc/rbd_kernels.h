@@ -1174,7 +1174,32 @@ __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(c
                             acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
                 }
             }
-            // r = X - Y C, squared and summed per column
+            // r = X - Y C, squared and summed per column.  Every entry is loaded
+            // before any is used, from a clamped address (row rbeg, column
+            // cols[0] stand in outside the tile) and without a branch: a guarded
+            // load used at once waits for its data before the next one issues.
+            if (!kResidPrefetchX) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int col = cols[16 * b + lr];
+                    const int colc = col >= 0 ? col : cols[0];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
+                            xr[a][b][r] = X[(row < rend ? row : rbeg) * ldx + colc];
+                        }
+                }
+            }
+            double wt[2][4];         // row weights, loaded the same way
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
+                    wt[a][r] = (!STORE && w) ? w[row < rend ? row : rbeg] : 1.0;
+                }
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int col = cols[16 * b + lr];
@@ -1183,12 +1208,13 @@ __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(c
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t row = row0 + 32 * wv + 16 * a + 4 * r + lk;
-                        if (row < rend && col >= 0) {
-                            const double xv = kResidPrefetchX ? Ld<Tx>::from(xr[a][b][r])
-                                                              : Ld<Tx>::one(X + row * ldx + col);
-                            const double d = xv - acc[a][b][r];
-                            if (STORE) R[row * ldr + t * TN + 16 * b + lr] = d;
-                            else rs[b] = w ? fma(w[row] * d, d, rs[b]) : fma(d, d, rs[b]);
+                        const bool in = row < rend && col >= 0;
+                        const double d = in ? Ld<Tx>::from(xr[a][b][r]) - acc[a][b][r] : 0.0;
+                        if (STORE) {
+                            if (in) R[row * ldr + t * TN + 16 * b + lr] = d;
+                        } else {
+                            // outside the tile d = 0 adds exactly nothing
+                            rs[b] = w ? fma(wt[a][r] * d, d, rs[b]) : fma(d, d, rs[b]);
                         }
                     }
             }
