@@ -101,12 +101,28 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_slab);
     const int nr = (int)(r1 - r0);
     if (WTS) {
+        // eight rows per thread per round, every load issued before any value is
+        // used (clamped rows past the slab's end are loaded and not stored)
         const double inv = DOT ? st->inv_nu : 1.0;
-        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
-            const double xi = v2[r0 + r] * inv;
-            xi_s[r] = xi;
-            if (TWO) xi_s[rows_per_slab + r] = g2[r0 + r];
-            if (DOT && dcol >= 0 && tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
+        constexpr int kSt = 8;
+        for (int rb = threadIdx.x; rb < nr; rb += kSt * (int)blockDim.x) {
+            double xv[kSt], gv[kSt];
+#pragma unroll
+            for (int u = 0; u < kSt; ++u) {
+                const int64_t rr = r0 + min(rb + u * (int)blockDim.x, nr - 1);
+                xv[u] = v2[rr];
+                gv[u] = TWO ? g2[rr] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSt; ++u) {
+                const int r = rb + u * (int)blockDim.x;
+                const double xi = xv[u] * inv;
+                if (r < nr) {
+                    xi_s[r] = xi;
+                    if (TWO) xi_s[rows_per_slab + r] = gv[u];
+                    if (DOT && dcol >= 0 && tile == 0) Y[(r0 + r) * ldy + dcol] = xi;
+                }
+            }
         }
         __syncthreads();
     }
