@@ -70,10 +70,14 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int kProjCols = 256;      // columns per workgroup
 // k-steps per load group: the register budget of two waves per SIMD (measured
 // on MI355X: one wave per SIMD left the matrix cores idle most of the time)
-template <typename Tv, int MT> constexpr int proj_group() {
-    return (sizeof(Tv) == 8 && MT == 4) ? 1 : ((sizeof(Tv) == 8 || MT == 4) ? 2 : 4);
+template <typename Tv, int MT> constexpr int proj_regs() {
+    return (sizeof(Tv) == 8 && MT == 4) ? 2 : ((sizeof(Tv) == 8 || MT == 4) ? 4 : 8);
 }
-constexpr int kProjStepMax = 16;    // the largest 4 * proj_group
+// ... held as B buffers of G k-steps (B * G = proj_regs): while one buffer is
+// multiplied, B - 1 are in flight
+template <typename Tv, int MT> constexpr int proj_group() { return proj_regs<Tv, MT>() >= 8 ? 2 : 1; }
+template <typename Tv, int MT> constexpr int proj_bufs() { return proj_regs<Tv, MT>() / proj_group<Tv, MT>(); }
+constexpr int kProjStepMax = 16;    // row chunks of a k-split are a multiple of this
 
 template <typename Tv, int MT>
 __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m, int d,
@@ -93,10 +97,9 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict
     for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[t][e] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
-    // two register buffers of G k-steps: the next group loads while the current one is multiplied
-    constexpr int kProjGroup = proj_group<Tv, MT>();
-    double a0[kProjGroup][MT], a1[kProjGroup][MT];
-    Raw4<Tv> b0[kProjGroup], b1[kProjGroup];
+    constexpr int kProjGroup = proj_group<Tv, MT>(), kBufs = proj_bufs<Tv, MT>();
+    double a[kBufs][kProjGroup][MT];
+    Raw4<Tv> b[kBufs][kProjGroup];
     auto load = [&](double (&a)[kProjGroup][MT], Raw4<Tv> (&b)[kProjGroup], int64_t k0) {
 #pragma unroll
         for (int g = 0; g < kProjGroup; ++g) {
@@ -123,17 +126,20 @@ __global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict
                     acc[t][e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[g][t], be, acc[t][e], 0, 0, 0);
             }
     };
-    // Two groups per iteration and a single exit (an exit between the two halves
-    // made the compiler keep two sets of accumulators: 1 wave per SIMD).  Loads
-    // past the end of the chunk give zeros, so an odd group count costs one
-    // group of products with zeros.
+    // B groups per iteration, the buffers in rotation, and a single exit (an
+    // exit inside the rotation made the compiler keep two sets of
+    // accumulators: 1 wave per SIMD).  Loads past the end of the chunk give
+    // zeros, so a group count that is not a multiple of B costs up to B - 1
+    // groups of products with zeros.
     constexpr int kStep = 4 * kProjGroup;
-    load(a0, b0, kb);
-    for (int64_t k0 = kb; k0 < ke; k0 += 2 * kStep) {
-        load(a1, b1, k0 + kStep);
-        mult(a0, b0);
-        load(a0, b0, k0 + 2 * kStep);
-        mult(a1, b1);
+#pragma unroll
+    for (int q = 0; q + 1 < kBufs; ++q) load(a[q], b[q], kb + q * kStep);
+    for (int64_t k0 = kb; k0 < ke; k0 += kBufs * kStep) {
+#pragma unroll
+        for (int q = 0; q < kBufs; ++q) {
+            load(a[(q + kBufs - 1) % kBufs], b[(q + kBufs - 1) % kBufs], k0 + (q + kBufs - 1) * kStep);
+            mult(a[q], b[q]);
+        }
     }
     double* out = part ? part + (int64_t)blockIdx.z * d * N : C;
     const int64_t ldo = part ? N : ldc;
