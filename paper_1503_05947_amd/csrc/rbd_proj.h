@@ -14,15 +14,15 @@ namespace rbd {
 inline int64_t proj_cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
-// proj_mfma: C = Y(:, 0:d)' V for a small d (d x N result), on the FP64
-// matrix cores.  Y is m x d FP64 row-major (ldy), V is m x N row-major (ldv)
-// stored as Tv.  A workgroup owns MT*16 <= 64 rows of C (grid.y) and 256
-// columns (grid.x, 64 per wave); grid.z splits the k range (rows of Y and V),
-// writing partials when it is larger than 1.  MFMA operands (16x16x4): lane l
-// supplies A(l % 16, l / 16) = Y(k0 + l/16, i0 + l % 16) and, for the e-th
-// 16-column tile, B(l / 16, l % 16) = V(k0 + l/16, j0 + 4 (l % 16) + e): each
-// lane reads four adjacent columns of V with one vector load, and the
-// results are written back through the same column permutation.
+// proj_mfma: C = Y(:, 0:d)' V (d x N result) on the FP64 matrix cores.  Y
+// is m x d FP64 row-major (ldy), V is m x N row-major (ldv) stored as Tv.  A
+// workgroup owns MT*16 <= 64 rows of C (grid.y) and 256 columns (grid.x, 64
+// per wave); grid.z splits the k range (rows of Y and V), writing partials
+// when it is larger than 1.  MFMA operands (16x16x4): lane l supplies
+// A(l % 16, l / 16) = Y(k0 + l/16, i0 + l % 16) and, for the e-th 16-column
+// tile, B(l / 16, l % 16) = V(k0 + l/16, j0 + 4 (l % 16) + e): each lane
+// reads four adjacent columns of V with one vector load, and the results are
+// written back through the same column permutation.
 // ---------------------------------------------------------------------------
 // Four adjacent stored values of V, kept in their storage format until use.
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
@@ -68,8 +68,9 @@ template <> struct Raw4<f16_t> : Raw4Half<f16_t> {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int kProjCols = 256;      // columns per workgroup
-// k-steps per load group: the register budget of two waves per SIMD (measured
-// on MI355X: one wave per SIMD left the matrix cores idle most of the time)
+// k-steps of operands held in registers: the budget of two waves per SIMD
+// (measured on MI355X: one wave per SIMD left the matrix cores idle most of
+// the time) ...
 template <typename Tv, int MT> constexpr int proj_regs() {
     return (sizeof(Tv) == 8 && MT == 4) ? 2 : ((sizeof(Tv) == 8 || MT == 4) ? 4 : 8);
 }
