@@ -1466,7 +1466,8 @@ __global__ void sum_rows_kernel(const double* __restrict__ part, int S, int64_t 
                                 int take_sqrt) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
-        for (int q = 0; q < S; ++q) s += part[(int64_t)q * len + e];
+#pragma unroll 8
+        for (int q = 0; q < S; ++q) s += part[(int64_t)q * len + e];      // eight loads in flight, ascending q
         out[e] = take_sqrt ? sqrt(s) : s;
     }
 }
