@@ -11,6 +11,11 @@ Contents
 ``rbd_fit``      Algorithm 1 of the paper (section 3.1), step by step, in FP64:
                  explicit residual, errors evaluated by their definition in
                  step 2.3 (no downdating), Gram-Schmidt done twice.
+``rbd_fit_gram`` Algorithm 1 with A = I carried out on the Gram matrix
+                 G = X'X alone (for inputs too large to hold in FP64 on the
+                 host): the new row of T and every error follow from G by
+                 eq. (3); the steps are those of ``rbd_fit``.
+``gram``         G = X'X accumulated in FP64 from row blocks of X.
 ``rbd_brute``    Brute-force greedy for tiny inputs: every step re-derives each
                  column's projection error from a fresh QR of the chosen
                  columns (section 3.1, step 2.3 by definition).
@@ -179,6 +184,102 @@ def rbd_fit(X, tol: float, d_max: int, rel: bool = False, start: int = -1, weigh
     return OracleFit(Y=Y[:, :d].copy(), T=T[:d].copy(), pivots=np.array(pivots, dtype=np.int64),
                      col_err=e, err_hist=np.array(err_hist),
                      gap_hist=np.array(gap_hist), d=d, tau=tau, stop=stop)
+
+
+@dataclass
+class GramFit:
+    T: np.ndarray          # (d, n) rows of T = Y' X
+    pivots: np.ndarray     # (d,)
+    col_err: np.ndarray    # (n,) errors after the last step, 0 for pivots
+    err_hist: np.ndarray   # (d+1,)
+    gap_hist: np.ndarray   # (d+1,) as in OracleFit
+    nu: np.ndarray         # (d,) the norm of each orthogonalised pivot column
+    d: int
+    tau: float
+    stop: str
+
+
+def gram(blocks):
+    """G = X'X in FP64, summed over row blocks of X (an iterable of (rows, n) arrays)."""
+    G = None
+    for B in blocks:
+        B = np.asarray(B, dtype=np.float64)
+        P = B.T @ B
+        G = P if G is None else G + P
+    return G
+
+
+def gram_row(G_p, c_p, T_prev, nu):
+    """The new row of T from the Gram matrix: xi' x_j = (G[p, j] - c_p' T(:, j)) / nu."""
+    return (G_p - c_p @ T_prev) / nu
+
+
+def gram_err2(diag, T_cur):
+    """eq. (3) with A = I and orthonormal Y: ||x_j - Y T(:, j)||^2 = G[j, j] - ||T(:, j)||^2."""
+    return diag - np.einsum("kj,kj->j", T_cur, T_cur)
+
+
+def rbd_fit_gram(G, tol: float, d_max: int, m: int, rel: bool = False, start: int = -1) -> GramFit:
+    """Algorithm 1 with A = I (section 3.1) when only G = X'X is at hand.
+
+    The basis vector of step 2.2 is xi = (x_p - Y c_p) / nu with c_p = Y' x_p =
+    T(:, p), so its inner product with any column is
+    xi' x_j = (G[p, j] - c_p' T(:, j)) / nu: the new row of T.  With Y
+    orthonormal, eq. (3) for A = I gives every error of step 2.3 as
+    e_j^2 = G[j, j] - ||T(:, j)||^2, and the norm of the orthogonalised pivot
+    column is nu = e_p.  Pivots are masked, ties go to the lowest index and
+    the break / stop tests are those of ``rbd_fit``.  Only the basis itself is
+    not formed.  G squares the data's condition number: errors below about
+    1e-7 of the largest column norm (for X with a million rows in FP64) carry
+    no correct digits.
+    """
+    G = np.asarray(G, dtype=np.float64)
+    n = G.shape[0]
+    if G.shape != (n, n) or n < 1 or m < 1 or d_max < 1:
+        raise ValueError("G must be n x n, m >= 1, d_max >= 1")
+    if not np.all(np.isfinite(G)):
+        raise FloatingPointError("G holds a non-finite value")
+    D = min(int(d_max), m, n)
+    diag = np.diag(G).copy()
+    e = np.sqrt(np.maximum(diag, 0.0))
+    E0 = float(e.max())
+    tau = float(tol) * E0 if rel else float(tol)
+    T = np.zeros((D, n))
+    chosen = np.zeros(n, dtype=bool)
+    pivots, nus = [], []
+    err_hist = [E0]
+    gap_hist = [_gap(e, E0)]
+    i = int(start) if start >= 0 else _lowest_argmax(e)
+    if not 0 <= i < n:
+        raise ValueError("start column out of range")
+    d = 0
+    E_cur = np.inf
+    stop = "dmax"
+    while d < D and E_cur > tau:
+        # 2.1-2.2: the orthogonalised pivot column, through its inner products
+        c_p = T[:d, i]
+        nu2 = float(diag[i] - c_p @ c_p)
+        nu = float(np.sqrt(nu2)) if nu2 > 0.0 else 0.0
+        if nu < tau or nu == 0.0:
+            stop = "break"
+            break
+        T[d, :] = gram_row(G[i, :], c_p, T[:d, :], nu)
+        chosen[i] = True
+        pivots.append(i)
+        nus.append(nu)
+        d += 1
+        # 2.3: eq. (3), every column from its Gram diagonal and its coefficients
+        e = np.sqrt(np.maximum(gram_err2(diag, T[:d]), 0.0))
+        e[chosen] = 0.0
+        E_cur = float(e.max())
+        gap_hist.append(_gap(e[~chosen], E0) if (~chosen).sum() >= 2 else np.inf)
+        i = _lowest_argmax(e)
+        err_hist.append(E_cur)
+        if E_cur <= tau:
+            stop = "tol"
+    return GramFit(T=T[:d].copy(), pivots=np.array(pivots, dtype=np.int64), col_err=e,
+                   err_hist=np.array(err_hist), gap_hist=np.array(gap_hist), nu=np.array(nus),
+                   d=d, tau=tau, stop=stop)
 
 
 def eq3_error(x, Y, c, weights=None, A=None):

@@ -1,17 +1,63 @@
 """Comparison of a device fit with the FP64 oracle (shared by the GPU tests and smoke).
 
-Protocol: pivots must agree on the prefix of steps at which the oracle's two
-largest errors are separated by more than ``gap`` * E_0; on that prefix the
-basis vectors, rows of T, error history and final errors must agree to
-``rtol`` (relative to 1 for unit vectors, to ||x_j|| for T columns, to E_0 for
-errors).  d must agree unless the oracle's last error is within 1e-3 tau of
-the tolerance or the prefix ended early.  Beyond the prefix, the device
-result must still satisfy the invariants (orthonormal Y, T = Y'X, certified
-errors) on its own.
+Several results are correct when two columns' errors are equal within the
+working precision (the order of a near-tie), so the protocol has two parts:
+
+1. Element by element on the separated prefix: the steps at which the
+   oracle's two largest errors differ by more than ``gap`` * E_0.  There the
+   pivots must be equal, and the basis vectors, rows of T and error history
+   must agree to ``rtol`` (relative to 1 for unit vectors, to ||x_j|| for T
+   columns, to E_0 for errors).
+
+2. At every step, on the device's own result (Algorithm 1, step 2.3 defines
+   the pivot as the argmax of the errors): the host recomputes in FP64 every
+   column's error against the device's first k basis vectors and rows of T.
+   Device pivot k must attain that maximum to within
+   ``gap`` * E_0 + ``choice_rel`` * E_k, and err_hist[k] must equal it to
+   within ``rtol`` * E_0.  The final errors must be the true residual norms.
+
+The final error E_d is compared with the oracle's whatever d is: to within
+``rtol`` * E_0, or, when d differs, the device's E_d may instead lie within
+1e-3 tau of the tolerance tau.  d must equal the oracle's after a fully
+separated run (unless E_d is that close to tau).  Every device result must
+also satisfy, on its own: Y'Y = I to 1e-12, T = Y'X, distinct pivots, a
+non-increasing history (A = I), and the Eckart-Young bounds of the SVD for
+the residual X - Y T.
+
+``compare_fit`` returns a list of failure messages (empty on success) that
+also carries what was compared: ``prefix`` (steps compared element by
+element), ``steps_checked`` (pivots checked as valid greedy choices),
+``worst_choice`` (largest shortfall of a device pivot below the true maximum,
+in units of E_0) and ``worst_hist`` (largest |err_hist[k] - true E_k| / E_0).
 """
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
+
+# choice tolerance relative to the current largest error: the device's
+# certified indicator is refreshed exactly once its downdated square falls
+# below 2^-20 of the last exact value, which keeps every indicator within
+# about 1.5e-7 of the column's own error; two columns closer than this are
+# a near-tie whose order is not fixed by the working precision.
+CHOICE_REL = 1e-6
+
+
+class ParityReport(list):
+    """Failure messages (a list, empty when the device result passes) plus statistics."""
+
+    prefix = 0
+    steps_checked = 0
+    worst_choice = 0.0
+    worst_hist = 0.0
+    d_dev = 0
+    d_ref = 0
+
+    def summary(self) -> str:
+        return (f"prefix {self.prefix}/{self.d_ref}, pivots checked {self.steps_checked}/{self.d_dev}, "
+                f"worst choice shortfall {self.worst_choice:.2e} E0, worst history error {self.worst_hist:.2e} E0")
 
 
 def separated_prefix(ref, gap: float) -> int:
@@ -21,61 +67,142 @@ def separated_prefix(ref, gap: float) -> int:
     return ref.d
 
 
-def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-6, exact_d: bool = True, weights=None,
-                norms=None):
-    """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values;
-    weights: the diagonal of A when the errors are A-norms (eq. (3)), else None;
-    norms: a callable giving the column A-norms of a matrix, for a general A."""
-    msgs = []
-    E0 = ref.err_hist[0]
-    k = min(separated_prefix(ref, gap), dev["d"], ref.d)
-    piv_ok = np.array_equal(dev["pivots"][:k], ref.pivots[:k])
-    if not piv_ok:
-        first = int(np.argmax(dev["pivots"][:k] != ref.pivots[:k]))
-        msgs.append(f"pivots differ at step {first} (prefix {k}): {dev['pivots'][:k]} vs {ref.pivots[:k]}")
-        return msgs
-    if k:
-        dy = np.max(np.abs(dev["Y"][:, :k] - ref.Y[:, :k]))
-        if dy > rtol:
-            msgs.append(f"Y differs by {dy:.3e}")
-        nx = np.linalg.norm(X, axis=0)
-        dt = np.linalg.norm(dev["T"][:k] - ref.T[:k], axis=0)
-        bad = dt > rtol * np.maximum(nx, 1e-300)
-        if bad.any():
-            msgs.append(f"T differs in {bad.sum()} columns (worst {np.max(dt / np.maximum(nx, 1e-300)):.3e})")
-        dh = np.max(np.abs(dev["err_hist"][: k + 1] - ref.err_hist[: k + 1]))
-        if dh > rtol * E0:
-            msgs.append(f"err_hist differs by {dh / E0:.3e} E0")
-    full = (k == ref.d == dev["d"])
-    if full:
-        de = np.max(np.abs(dev["col_err"] - ref.col_err))
-        if de > rtol * E0:
-            msgs.append(f"col_err differs by {de / E0:.3e} E0")
-    near_tol = ref.tau > 0 and abs(ref.err_hist[-1] - ref.tau) <= 1e-3 * ref.tau
-    if exact_d and k == ref.d and dev["d"] != ref.d and not near_tol:
-        msgs.append(f"d differs after a fully separated run: {dev['d']} vs {ref.d}")
-    if dev["d"] == ref.d and abs(dev["err_hist"][dev["d"]] - ref.err_hist[ref.d]) > rtol * E0:
-        msgs.append("final error differs: %.6e vs %.6e" % (dev["err_hist"][dev["d"]], ref.err_hist[ref.d]))
-    msgs += invariant_msgs(dev, X, rtol, weights=weights, norms=norms)
-    return msgs
-
-
 def _norms(R, weights, norms=None):
     if norms is not None:
         return norms(R)
     if weights is None:
-        return np.linalg.norm(R, axis=0)
+        return np.sqrt(np.einsum("ij,ij->j", R, R))
     return np.sqrt(np.asarray(weights, dtype=np.float64) @ (R * R))
 
 
-def invariant_msgs(dev, X, rtol=1e-5, weights=None, norms=None):
-    """Checks a device fit on its own: orthonormal Y, T = Y'X, certified errors, monotone history
-    (with A = I: a Euclidean projection residual can grow in another A-norm)."""
+def greedy_trace(dev, X, weights=None, norms=None):
+    """Replays the device's steps on the host in FP64.
+
+    For k = 0..d yields (k, e) where e[j] is column j's error against the
+    device's first k basis vectors and rows of T (step 2.3's definition,
+    ||x_j - Y(:, :k) T(:k, j)|| in the chosen norm), with the device's first
+    k pivots masked to 0.  The residual is updated one rank-one term per step.
+    """
+    d = dev["d"]
+    Y, T, piv = dev["Y"], dev["T"], dev["pivots"]
+    R = np.array(X, dtype=np.float64, copy=True)
+    chosen = np.zeros(R.shape[1], dtype=bool)
+    for k in range(d + 1):
+        e = _norms(R, weights, norms)
+        e[chosen] = 0.0
+        yield k, e, R
+        if k < d:
+            R -= np.outer(Y[:, k], T[k])
+            chosen[int(piv[k])] = True
+
+
+def eckart_young_msgs(X, R, d: int):
+    """P9: a rank-d approximation cannot beat the truncated SVD.
+    ||R||_F^2 >= sum_{i >= d} sigma_i^2 and ||R||_2 >= sigma_d (0-based), with the
+    squared singular values taken as eigenvalues of the smaller Gram matrix."""
+    m, n = X.shape
+    r = min(m, n)
+    if d >= r:
+        return []
+
+    def gram(A):
+        return A @ A.T if m <= n else A.T @ A
+
+    slack = 64 * np.finfo(np.float64).eps * r
+    msgs = []
+    G = gram(X)
+    total = float(np.trace(G))
+    if r <= 2500:
+        lam = np.clip(np.linalg.eigvalsh(G)[::-1], 0.0, None)
+        tail = float(np.sum(lam[d:]))
+    else:                                   # only the d + 1 largest: the tail is the trace minus the rest
+        import scipy.linalg as sla
+        lam = np.clip(sla.eigvalsh(G, subset_by_index=[r - d - 1, r - 1])[::-1], 0.0, None)
+        tail = total - float(np.sum(lam[:d]))
+        slack *= d + 1
+    resF = float(np.sum(R * R))
+    if resF < tail - slack * total:
+        msgs.append(f"residual beats Eckart-Young in the Frobenius norm ({resF:.6e} < {tail:.6e})")
+    GR = gram(R)
+    if r <= 2500:
+        res2 = float(np.linalg.eigvalsh(GR)[-1])
+    else:
+        import scipy.linalg as sla
+        res2 = float(sla.eigvalsh(GR, subset_by_index=[r - 1, r - 1])[0])
+    if res2 < lam[d] - slack * lam[0]:
+        msgs.append(f"residual beats Eckart-Young in the 2-norm ({res2:.6e} < {lam[d]:.6e})")
+    return msgs
+
+
+def _log(report, label):
+    path = os.environ.get("RBD_PARITY_LOG")
+    if not path:
+        return
+    rec = dict(label=label or os.environ.get("PYTEST_CURRENT_TEST", ""), prefix=report.prefix, d_ref=report.d_ref, d_dev=report.d_dev,
+               steps_checked=report.steps_checked, worst_choice=report.worst_choice,
+               worst_hist=report.worst_hist, ok=(len(report) == 0), msgs=list(report))
+    with open(path, "a") as f:
+        f.write(json.dumps(rec) + "\n")
+
+
+def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-8, exact_d: bool = True, weights=None,
+                norms=None, choice_rel: float = CHOICE_REL, eckart_young: bool = True, label: str = ""):
+    """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values;
+    weights: the diagonal of A when the errors are A-norms (eq. (3)), else None;
+    norms: a callable giving the column A-norms of a matrix, for a general A."""
+    out = ParityReport()
+    X = np.asarray(X, dtype=np.float64)
+    E0 = ref.err_hist[0]
+    d = dev["d"]
+    out.d_dev, out.d_ref = d, ref.d
+
+    # 1. element by element on the separated prefix
+    k = min(separated_prefix(ref, gap), d, ref.d)
+    out.prefix = k
+    if not np.array_equal(dev["pivots"][:k], ref.pivots[:k]):
+        first = int(np.argmax(dev["pivots"][:k] != ref.pivots[:k]))
+        out.append(f"pivots differ at step {first} (prefix {k}): {dev['pivots'][:k]} vs {ref.pivots[:k]}")
+        _log(out, label)
+        return out
+    if k:
+        dy = np.max(np.abs(dev["Y"][:, :k] - ref.Y[:, :k]))
+        if dy > rtol:
+            out.append(f"Y differs by {dy:.3e}")
+        nx = np.linalg.norm(X, axis=0)
+        dt = np.linalg.norm(dev["T"][:k] - ref.T[:k], axis=0)
+        bad = dt > rtol * np.maximum(nx, 1e-300)
+        if bad.any():
+            out.append(f"T differs in {bad.sum()} columns (worst {np.max(dt / np.maximum(nx, 1e-300)):.3e})")
+        dh = np.max(np.abs(dev["err_hist"][: k + 1] - ref.err_hist[: k + 1]))
+        if dh > rtol * E0:
+            out.append(f"err_hist differs by {dh / E0:.3e} E0")
+    if k == ref.d == d:
+        de = np.max(np.abs(dev["col_err"] - ref.col_err))
+        if de > rtol * E0:
+            out.append(f"col_err differs by {de / E0:.3e} E0")
+
+    # the final error and d
+    Ed_dev, Ed_ref = dev["err_hist"][d], ref.err_hist[ref.d]
+    near_tol = ref.tau > 0 and (abs(Ed_ref - ref.tau) <= 1e-3 * ref.tau or abs(Ed_dev - ref.tau) <= 1e-3 * ref.tau)
+    if exact_d and k == ref.d and d != ref.d and not near_tol:
+        out.append(f"d differs after a fully separated run: {d} vs {ref.d}")
+    if abs(Ed_dev - Ed_ref) > rtol * E0 and not (d != ref.d and near_tol):
+        out.append("final error differs: %.6e (d=%d) vs %.6e (d=%d)" % (Ed_dev, d, Ed_ref, ref.d))
+
+    # 2. every step: a valid greedy choice against the device's own basis
+    out += _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young)
+    _log(out, label)
+    return out
+
+
+def _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young):
     msgs = []
     d = dev["d"]
+    piv = dev["pivots"]
     Y, T = dev["Y"][:, :d], dev["T"][:d]
+    E0 = float(_norms(X, weights, norms).max())
+    scale = max(E0, 1e-300)
     nx = np.linalg.norm(X, axis=0)
-    E0 = _norms(X, weights, norms).max()
     if d:
         o = np.max(np.abs(Y.T @ Y - np.eye(d)))
         if o > 1e-12:
@@ -83,15 +210,54 @@ def invariant_msgs(dev, X, rtol=1e-5, weights=None, norms=None):
         dt = np.max(np.abs(T - Y.T @ X))
         if dt > 1e-12 * max(nx.max(), 1e-300) * np.sqrt(X.shape[0]):
             msgs.append(f"T != Y'X ({dt:.2e})")
-    true_err = _norms(X - Y @ T, weights, norms)
-    if d:
-        true_err[dev["pivots"][:d]] = 0.0
-    de = np.max(np.abs(true_err - dev["col_err"]))
-    if de > rtol * max(E0, 1e-300):
-        msgs.append(f"col_err not the true residual norm ({de / max(E0, 1e-300):.2e} E0)")
-    h = dev["err_hist"][: d + 1]
-    if weights is None and norms is None and np.any(np.diff(h) > 1e-9 * max(E0, 1e-300)):
-        msgs.append("error history increases")
-    if len(set(dev["pivots"][:d].tolist())) != d:
+    if len(set(piv[:d].tolist())) != d:
         msgs.append("repeated pivot")
+        return msgs
+    h = dev["err_hist"][: d + 1]
+    if weights is None and norms is None and np.any(np.diff(h) > 1e-9 * scale):
+        msgs.append("error history increases")
+
+    worst_choice = worst_hist = 0.0
+    bad_choice = bad_hist = None
+    R = None
+    for k, e, R in greedy_trace(dev, X, weights, norms):
+        Ek = float(e.max())
+        hk = abs(float(h[k]) - Ek) / scale
+        worst_hist = max(worst_hist, hk)
+        if hk > rtol and bad_hist is None:
+            bad_hist = f"err_hist[{k}] = {h[k]:.9e} but the true largest error is {Ek:.9e}"
+        if k < d:
+            p = int(piv[k])
+            if k == 0 and len(ref.pivots) and p == int(ref.pivots[0]):
+                continue                      # the first column: greedy or the user's start, as the oracle's
+            short = Ek - float(e[p])
+            worst_choice = max(worst_choice, short / scale)
+            if short > gap * E0 + choice_rel * Ek and bad_choice is None:
+                bad_choice = (f"pivot {p} at step {k} has true error {e[p]:.9e}, "
+                              f"below the largest {Ek:.9e} (column {int(np.argmax(e))})")
+        else:
+            de = np.max(np.abs(e - dev["col_err"]))
+            if de > rtol * scale:
+                msgs.append(f"col_err not the true residual norm ({de / scale:.2e} E0)")
+    out.steps_checked = d
+    out.worst_choice, out.worst_hist = worst_choice, worst_hist
+    if bad_choice:
+        msgs.append(bad_choice)
+    if bad_hist:
+        msgs.append(bad_hist)
+    if eckart_young and R is not None:
+        msgs += eckart_young_msgs(X, R, d)
     return msgs
+
+
+def invariant_msgs(dev, X, rtol=1e-5, weights=None, norms=None):
+    """Checks a device fit on its own (no oracle): orthonormal Y, T = Y'X, every pivot a
+    valid greedy choice, certified errors, monotone history (A = I), Eckart-Young."""
+
+    class _NoRef:
+        pivots = np.zeros(0, dtype=np.int64)
+
+    out = ParityReport()
+    out += _choice_and_invariant_msgs(out, dev, np.asarray(X, dtype=np.float64), rtol, 1e-8, CHOICE_REL,
+                                      weights, norms, _NoRef, True)
+    return out

@@ -45,11 +45,12 @@ def run_fit(stored, dtype, tol, d_max, rel=False, start=-1, pad_cols=0):
                 stop=res.stop)
 
 
-def check(name, stored, vals, dtype, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-6, exact_d=True):
+def check(name, stored, vals, dtype, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-8, exact_d=True):
     print(f"[gpu] {name} dtype={dtype} shape={vals.shape} tol={tol} rel={rel} d_max={d_max}", flush=True)
     dev = run_fit(stored, dtype, tol, d_max, rel=rel, start=start, pad_cols=pad_cols)
     ref = oracle.rbd_fit(vals, tol, d_max, rel=rel, start=start)
     msgs = compare_fit(dev, ref, vals, gap=gap, exact_d=exact_d)
+    print(f"[gpu] {name}: {msgs.summary()}", flush=True)
     assert msgs == [], f"{name}: " + "; ".join(msgs)
     return dev, ref
 
@@ -83,6 +84,14 @@ def test_bump_field_full_size_f32():
     stored, vals = synth.quantize(w.X, "f32")
     dev, ref = check("bump_field 2048^2", stored, vals, "f32", w.tol, w.d_max, rel=True)
     assert dev["stop"] == "tol"
+
+
+def test_bump_field_full_size_f64_exact_pivots():
+    """FP64 storage: the device must reproduce the oracle's pivots and d exactly."""
+    w = synth.bump_field(0)
+    stored, vals = synth.quantize(w.X, "f64")
+    dev, ref = check("bump_field 2048^2 f64", stored, vals, "f64", w.tol, w.d_max, rel=True)
+    assert dev["d"] == ref.d and np.array_equal(dev["pivots"], ref.pivots)
 
 
 def test_bump_field_f64_exact_pivots():

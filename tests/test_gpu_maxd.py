@@ -35,7 +35,7 @@ def test_identity_at_max_d(gauss):
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=D))
     ref = oracle.rbd_fit(vals, 0.0, D)
     assert dev["d"] == D == ref.d
-    msgs = compare_fit(dev, ref, vals, gap=1e-6)
+    msgs = compare_fit(dev, ref, vals)
     assert msgs == [], "; ".join(msgs)
 
 
@@ -47,7 +47,7 @@ def test_diagonal_at_max_d(gauss):
     print(f"[gpu] max d diagonal {M}x{N} d_max={D}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=D, weights=torch.from_numpy(w).to("cuda:0")))
     ref = oracle.rbd_fit(vals, 0.0, D, weights=w)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6, weights=w)
+    msgs = compare_fit(dev, ref, vals, weights=w)
     assert msgs == [], "; ".join(msgs)
 
 
@@ -60,7 +60,7 @@ def test_spd_at_max_d(gauss):
     print(f"[gpu] max d spd {M}x{N} d_max={D}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=D, A=device_csr(ip, ix, av)))
     ref = oracle.rbd_fit(vals, 0.0, D, A=A)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6, norms=lambda R: _norms_A(R, A))
+    msgs = compare_fit(dev, ref, vals, norms=lambda R: _norms_A(R, A))
     assert msgs == [], "; ".join(msgs)
 
 
@@ -77,5 +77,5 @@ def test_extreme_shapes(m, n, d_max):
     print(f"[gpu] extreme shape {m}x{n} d_max={d_max}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=d_max))
     ref = oracle.rbd_fit(vals, 0.0, d_max)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6)
+    msgs = compare_fit(dev, ref, vals)
     assert msgs == [], "; ".join(msgs)

@@ -35,7 +35,7 @@ def run(stored, dtype, csr, tol, d_max, rel=False, start=-1, pad_cols=0):
                 col_err=res.col_err.cpu().numpy(), err_hist=res.err_hist.cpu().numpy(), d=res.d, stop=res.stop)
 
 
-def check(name, stored, vals, dtype, csr, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-6):
+def check(name, stored, vals, dtype, csr, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-8):
     m = vals.shape[0]
     print(f"[gpu] spd {name} dtype={dtype} shape={vals.shape} nnz={len(csr[2])} tol={tol} d_max={d_max}",
           flush=True)

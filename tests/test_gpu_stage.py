@@ -37,7 +37,7 @@ def test_identity_every_final_block_residue(field, d_max):
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=d_max))
     ref = oracle.rbd_fit(vals, 0.0, d_max)
     assert dev["d"] == d_max
-    msgs = compare_fit(dev, ref, vals, gap=1e-6)
+    msgs = compare_fit(dev, ref, vals)
     assert msgs == [], "; ".join(msgs)
 
 
@@ -50,7 +50,7 @@ def test_diagonal_every_final_block_residue(field, d_max):
     print(f"[gpu] stage diagonal d_max={d_max}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=d_max, weights=torch.from_numpy(w).to("cuda:0")))
     ref = oracle.rbd_fit(vals, 0.0, d_max, weights=w)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6, weights=w)
+    msgs = compare_fit(dev, ref, vals, weights=w)
     assert msgs == [], "; ".join(msgs)
 
 
@@ -64,7 +64,7 @@ def test_spd_every_final_block_residue(field, d_max):
     print(f"[gpu] stage spd d_max={d_max}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=d_max, A=device_csr(ip, ix, av)))
     ref = oracle.rbd_fit(vals, 0.0, d_max, A=A)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6, norms=lambda R: _norms_A(R, A))
+    msgs = compare_fit(dev, ref, vals, norms=lambda R: _norms_A(R, A))
     assert msgs == [], "; ".join(msgs)
 
 
@@ -77,7 +77,7 @@ def test_refresh_inside_a_block_then_more_steps():
     print("[gpu] stage refresh inside a block", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=wl.tol, d_max=wl.d_max))
     ref = oracle.rbd_fit(vals, wl.tol, wl.d_max)
-    msgs = compare_fit(dev, ref, vals, gap=1e-6)
+    msgs = compare_fit(dev, ref, vals)
     assert msgs == [], "; ".join(msgs)
     Y = dev["Y"]
     assert np.max(np.abs(Y.T @ Y - np.eye(dev["d"]))) < 1e-12

@@ -26,7 +26,7 @@ def run(stored, dtype, w, tol, d_max, rel=False, start=-1, pad_cols=0):
                 stop=res.stop)
 
 
-def check(name, stored, vals, dtype, w, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-6):
+def check(name, stored, vals, dtype, w, tol, d_max, rel=False, start=-1, pad_cols=0, gap=1e-8):
     print(f"[gpu] weighted {name} dtype={dtype} shape={vals.shape} tol={tol} rel={rel} d_max={d_max}",
           flush=True)
     dev = run(stored, dtype, w, tol, d_max, rel=rel, start=start, pad_cols=pad_cols)
