@@ -57,7 +57,8 @@ enum {
     RBD_ENONFINITE = -2,  /* X holds NaN or Inf (device status only)              */
     RBD_EWORKSPACE = -3,  /* workspace smaller than the size query returned       */
     RBD_EDEVICE = -4,     /* a HIP launch or runtime call failed                  */
-    RBD_EMATRIX = -5      /* sparse A: an index outside its rows (device status)  */
+    RBD_EMATRIX = -5,     /* sparse A: an index outside its rows (device status)  */
+    RBD_ETOOLARGE = -6    /* rbd_fit_noalloc: the fit needs more than its scratch */
 };
 
 /* Why the greedy loop ended (written to stop_reason when non-NULL). */
@@ -114,6 +115,31 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
             double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
             int32_t* d_out, int32_t* status, int32_t* stop_reason,
             void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rbd_fit_noalloc -- rbd_fit for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation, kernels and results as rbd_fit with
+ * the same arguments, but no workspace argument.  The workspace is a fixed
+ * scratch array of RBD_NOALLOC_MAX_BYTES in the library's device code, one
+ * per GPU, held until the process ends; its device address is looked up once
+ * per device (on the first call with that device current).  The call
+ * allocates and frees nothing and never synchronises.
+ *   All arguments and outputs are those of rbd_fit; `stream` must belong to
+ *   the current device.
+ * Every call on one GPU shares that GPU's scratch: calls whose execution
+ * overlaps on one GPU (other streams, other host threads) race and give
+ * undefined results; serialise them (one stream, or events).  The scratch
+ * keeps the last call's contents; every call initialises what it reads.
+ * Returns RBD_ETOOLARGE (before any device call) when
+ * rbd_fit_workspace_size() exceeds RBD_NOALLOC_MAX_BYTES, else what rbd_fit
+ * returns; RBD_EDEVICE if the scratch address cannot be obtained.
+ */
+#define RBD_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int rbd_fit_noalloc(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
+                    double tol, rbd_tol_mode mode, int32_t d_max, int64_t start,
+                    double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                    int32_t* d_out, int32_t* status, int32_t* stop_reason, void* stream);
 
 /*
  * rbd_fit_weighted -- Algorithm 1 with the A-norm of section 3.2 for a general

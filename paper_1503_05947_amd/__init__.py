@@ -92,13 +92,13 @@ class FitBuffers:
     """Outputs and workspace of one rbd_fit configuration, reusable across calls
     (``spd``: sized for rbd_fit_spd as well)."""
 
-    def __init__(self, m: int, n: int, d_max: int, dtype, device, spd: bool = False):
+    def __init__(self, m: int, n: int, d_max: int, dtype, device, spd: bool = False, workspace: bool = True):
         torch = _torch()
         self.m, self.n, self.d_max, self.dtype = int(m), int(n), int(d_max), dtype
         code = dtype_code(dtype)
         self.spd = bool(spd)
         self.ws_bytes = (_lib.fit_spd_workspace_size if spd else _lib.fit_workspace_size)(
-            self.m, self.n, self.d_max, code)
+            self.m, self.n, self.d_max, code) if workspace else 0
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
         self.Y = torch.empty((self.m, self.d_max), **f64)
@@ -107,7 +107,8 @@ class FitBuffers:
         self.col_err = torch.empty(self.n, **f64)
         self.err_hist = torch.empty(self.d_max + 1, **f64)
         self.ints = torch.empty(4, dtype=torch.int32, device=dev)     # d, status, stop reason
-        self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self.workspace = (torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev) if workspace
+                          else None)
 
     def result(self) -> FitResult:
         d, status, stop = (int(v) for v in self.ints[:3].tolist())
@@ -156,6 +157,27 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
             rc = lib.rbd_fit_weighted(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0),
                                       weights.data_ptr(), float(tol), mode, bufs.d_max, int(start), *outs)
     _lib.check(rc, "rbd_fit")
+
+
+def fit_noalloc_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: int = -1,
+                     stream=None) -> None:
+    """Enqueue rbd_fit_noalloc (A = I) on ``stream``: rbd_fit with the library's fixed
+    per-device scratch in place of a workspace (``bufs`` may be created with
+    ``workspace=False``).  Calls that overlap on one GPU share that scratch."""
+    torch = _torch()
+    _check_matrix(X, "X")
+    if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
+        raise ValueError("X does not match the buffers' shape/dtype")
+    lib = load()
+    with torch.cuda.device(X.device):
+        s = stream if stream is not None else torch.cuda.current_stream(X.device)
+        ints = bufs.ints.data_ptr()
+        rc = lib.rbd_fit_noalloc(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol),
+                                 _lib.RBD_TOL_REL if rel else _lib.RBD_TOL_ABS, bufs.d_max, int(start),
+                                 bufs.Y.data_ptr(), bufs.T.data_ptr(), bufs.pivots.data_ptr(),
+                                 bufs.col_err.data_ptr(), bufs.err_hist.data_ptr(), ints, ints + 4, ints + 8,
+                                 s.cuda_stream)
+    _lib.check(rc, "rbd_fit_noalloc")
 
 
 class FitGraph:

@@ -12,7 +12,8 @@ RBD_F32, RBD_BF16, RBD_F16, RBD_F64 = 0, 1, 2, 3
 # rbd_tol_mode
 RBD_TOL_ABS, RBD_TOL_REL = 0, 1
 # status codes
-RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE, RBD_EMATRIX = 0, -1, -2, -3, -4, -5
+RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE, RBD_EMATRIX, RBD_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
+RBD_NOALLOC_MAX_BYTES = 64 << 20
 # stop reasons
 RBD_STOP_TOL, RBD_STOP_DMAX, RBD_STOP_BREAK = 1, 2, 3
 RBD_MAX_D = 1024
@@ -24,6 +25,8 @@ SIGNATURES = {
     "rbd_fit_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_fit": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbd_fit_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64,
+                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rbd_fit_weighted": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32, _i64,
                                         _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_fit_graph_create": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32,

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -798,6 +799,39 @@ int project_typed(const ProjPlan& P, const double* Y, int64_t ldy, int64_t m, in
 
 }  // namespace
 
+// Workspace of rbd_fit_noalloc: a fixed device array in this code object, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only stands for the symbol): its
+// device address is looked up once per device with that device current, and
+// only that address is used.
+static __device__ __align__(256) unsigned char scratch[RBD_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return RBD_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr ||
+            reinterpret_cast<uintptr_t>(ptr) % kAlign != 0) {
+            (void)hipGetLastError();
+            return RBD_EDEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBD_OK;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -811,17 +845,29 @@ int rbd_fit_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, si
     return RBD_OK;
 }
 
+// Host-side argument checks shared by rbd_fit and rbd_fit_noalloc (no device call).
+static int check_fit_args(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol,
+                          rbd_tol_mode mode, int32_t d_max, int64_t start, const double* Y, const double* T,
+                          const int64_t* pivots, const double* col_err, const double* err_hist, const int32_t* d_out,
+                          const int32_t* status, FitPlan* P) {
+    if (!make_fit_plan(m, n, d_max, xt, P)) return RBD_EINVAL;
+    if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status) return RBD_EINVAL;
+    if (ldx < n) return RBD_EINVAL;
+    if (!(tol >= 0.0) || tol == HUGE_VAL) return RBD_EINVAL;
+    if (mode != RBD_TOL_ABS && mode != RBD_TOL_REL) return RBD_EINVAL;
+    if (start >= n) return RBD_EINVAL;
+    return RBD_OK;
+}
+
 static int fit_entry(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
                      int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err,
                      double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace,
                      size_t workspace_bytes, void* stream, const double* w) {
     FitPlan P;
-    if (!make_fit_plan(m, n, d_max, xt, &P)) return RBD_EINVAL;
-    if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status || !workspace) return RBD_EINVAL;
-    if (ldx < n) return RBD_EINVAL;
-    if (!(tol >= 0.0) || tol == HUGE_VAL) return RBD_EINVAL;
-    if (mode != RBD_TOL_ABS && mode != RBD_TOL_REL) return RBD_EINVAL;
-    if (start >= n) return RBD_EINVAL;
+    const int rc = check_fit_args(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist,
+                                  d_out, status, &P);
+    if (rc != RBD_OK) return rc;
+    if (!workspace) return RBD_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return RBD_EINVAL;
     if (workspace_bytes < P.total) return RBD_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -850,6 +896,22 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, doub
             void* stream) {
     return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
                      stop_reason, workspace, workspace_bytes, stream, nullptr);
+}
+
+int rbd_fit_noalloc(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol,
+                    rbd_tol_mode mode, int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots,
+                    double* col_err, double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                    void* stream) {
+    FitPlan P;
+    const int rc = check_fit_args(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist,
+                                  d_out, status, &P);
+    if (rc != RBD_OK) return rc;
+    if (P.total > RBD_NOALLOC_MAX_BYTES) return RBD_ETOOLARGE;
+    void* ws = nullptr;
+    const int rs = noalloc_scratch(&ws);
+    if (rs != RBD_OK) return rs;
+    return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
+                     stop_reason, ws, RBD_NOALLOC_MAX_BYTES, stream, nullptr);
 }
 
 int rbd_fit_weighted(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, const double* weights,
@@ -1037,6 +1099,7 @@ const char* rbd_status_string(int code) {
         case RBD_EWORKSPACE: return "workspace too small";
         case RBD_EDEVICE: return "HIP launch or runtime error";
         case RBD_EMATRIX: return "sparse A holds an index outside its rows";
+        case RBD_ETOOLARGE: return "the fit needs more workspace than rbd_fit_noalloc's fixed scratch";
     }
     return "unknown status";
 }

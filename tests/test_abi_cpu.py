@@ -175,3 +175,22 @@ def test_fit_graph_rejects_the_null_stream(lib):
     assert rc == _lib.RBD_EINVAL
     assert lib.rbd_fit_graph_launch(None, None) == _lib.RBD_EINVAL
     assert lib.rbd_fit_graph_destroy(None) == _lib.RBD_OK
+
+
+def test_noalloc_rejects_before_any_device_call(lib):
+    """rbd_fit_noalloc: argument errors and sizes beyond its fixed scratch are
+    reported before the device is touched (this container has no GPU)."""
+    from paper_1503_05947_amd import _lib
+    fake = ctypes.c_void_p(4096)
+
+    def call(m, n, d_max, X=fake, ldx=None):
+        return lib.rbd_fit_noalloc(X, 0, m, n, n if ldx is None else ldx, 0.0, 0, d_max, -1, fake, fake, fake,
+                                   fake, fake, fake, fake, None, None)
+
+    assert call(1 << 20, 4096, 512) == _lib.RBD_ETOOLARGE
+    assert _lib.fit_workspace_size(1 << 20, 4096, 512, _lib.RBD_F32) > _lib.RBD_NOALLOC_MAX_BYTES
+    assert _lib.fit_workspace_size(2048, 2048, 256, _lib.RBD_F32) <= _lib.RBD_NOALLOC_MAX_BYTES
+    assert call(100, 100, 10, X=None) == _lib.RBD_EINVAL
+    assert call(100, 100, 10, ldx=99) == _lib.RBD_EINVAL
+    assert call(0, 100, 10) == _lib.RBD_EINVAL
+    assert lib.rbd_status_string(_lib.RBD_ETOOLARGE)
