@@ -391,7 +391,9 @@ enum {
     RBD_PHASE_RESID = 6,     /* exact residual norms of queued columns            */
     RBD_PHASE_RESID_FINISH = 7,
     RBD_PHASE_EPILOGUE = 8,
-    RBD_NUM_PHASES = 9
+    RBD_PHASE_LOOP = 9,      /* the persistent loop of a cache-resident fit: the  *
+                              * whole of Algorithm 1 in one launch                */
+    RBD_NUM_PHASES = 10
 };
 int rbd_profiler_begin(uint32_t phase_mask);
 int rbd_profiler_end(double* phase_ms, int64_t* phase_launches, int32_t nphase,

@@ -114,6 +114,8 @@ class FitBuffers:
         d, status, stop = (int(v) for v in self.ints[:3].tolist())
         if status == _lib.RBD_EMATRIX:
             raise ValueError(f"rbd_fit_spd: {status_string(status)}")
+        if status == _lib.RBD_EDEVICE:
+            raise RuntimeError(f"rbd_fit: {status_string(status)} (the persistent loop's workgroups were not all resident)")
         if status != _lib.RBD_OK:
             raise FloatingPointError(f"rbd_fit: {status_string(status)}")
         return FitResult(Y=self.Y[:, :d], T=self.T[:d], pivots=self.pivots[:d], col_err=self.col_err,

@@ -17,7 +17,7 @@ RBD_NOALLOC_MAX_BYTES = 64 << 20
 # stop reasons
 RBD_STOP_TOL, RBD_STOP_DMAX, RBD_STOP_BREAK = 1, 2, 3
 RBD_MAX_D = 1024
-PHASES = ("colnorm", "init", "cgs1", "cgs2", "xscan", "update", "resid", "resid_finish", "epilogue")
+PHASES = ("colnorm", "init", "cgs1", "cgs2", "xscan", "update", "resid", "resid_finish", "epilogue", "loop")
 
 # every symbol include/rbd.h declares, with its ctypes signature
 _i64, _i32, _sz, _vp, _dp = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -19,6 +20,7 @@
 
 #include "../../include/rbd.h"
 #include "rbd_kernels.h"
+#include "rbd_loop.h"
 #include "rbd_proj.h"
 
 namespace {
@@ -53,12 +55,59 @@ struct FitPlan {
     // exact residual evaluation
     int rc_rows = 0, rc_S = 0, rc_grid = 0, rf_grid = 0;
     int ntickets = 0;
+    // persistent loop (A = I, cache-resident X): workgroups, Gram-Schmidt
+    // workgroups, rows per Gram-Schmidt workgroup, columns per workgroup
+    bool loop = false;
+    int lp_G = 0, lp_Gc = 0, lp_RB = 0, lp_CW = 0;
+    size_t o_lp_bv = 0, o_lp_bi = 0, o_lp_bc = 0, o_lp_part = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
     size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_M, o_mh, o_hw, o_ys,
         o_part,
         o_l2, o_rpart, total;
 };
+
+// The persistent loop (rbd_loop.h) runs the whole fit in one launch when X is
+// small enough to stay in the caches from step to step; larger X streams from
+// HBM with one launch per kernel of a step.  RBD_LOOP=0 in the environment
+// turns the persistent loop off, RBD_LOOP=1 uses it whenever the shape allows,
+// RBD_LOOP_G sets its workgroup count (both for measurements); the workgroup
+// count assumes the MI355X's 256 CUs and is checked against the device at
+// launch.
+constexpr double kLoopMaxBytes = 64.0 * 1024 * 1024;
+constexpr int kLoopMaxG = 256;
+
+void plan_loop(FitPlan* P) {
+    P->loop = false;
+    const char* env = std::getenv("RBD_LOOP");
+    const int force = env ? std::atoi(env) : -1;
+    if (force == 0) return;
+    const double bytes = (double)P->m * (double)P->n * elem_bytes(P->xt);
+    if (force != 1 && bytes > kLoopMaxBytes) return;
+    if (P->m >= ((int64_t)1 << 30) || P->n >= ((int64_t)1 << 30)) return;
+    // one workgroup per 256 KB of X, a multiple of 8 (whole XCDs), 8 .. 256
+    int64_t G = (int64_t)(bytes / (256.0 * 1024));
+    G = std::max<int64_t>(8, std::min<int64_t>(kLoopMaxG, cdiv(std::max<int64_t>(G, 1), 8) * 8));
+    // at most kLoopMaxCW columns and kLoopMaxRB Gram-Schmidt rows per workgroup;
+    // up to 32 Gram-Schmidt workgroups of at least 64 rows
+    const int64_t Gc = std::max<int64_t>(cdiv(P->m, kLoopMaxRB), std::min<int64_t>(32, cdiv(P->m, 64)));
+    G = std::max<int64_t>(G, cdiv(cdiv(P->n, kLoopMaxCW), 8) * 8);
+    G = std::max<int64_t>(G, cdiv(Gc, 8) * 8);
+    if (const char* g_env = std::getenv("RBD_LOOP_G")) {      // measurement override, a multiple of 8
+        const int64_t g = std::atoll(g_env);
+        if (g >= 8 && g % 8 == 0) G = std::max<int64_t>(g, cdiv(Gc, 8) * 8);
+    }
+    if (G > kLoopMaxG) return;
+    const int64_t RB = cdiv(P->m, Gc);
+    int CW = 1;
+    while ((int64_t)CW * G < P->n) CW <<= 1;
+    if (CW > kLoopMaxCW || RB > kLoopMaxRB) return;
+    P->loop = true;
+    P->lp_G = (int)G;
+    P->lp_Gc = (int)Gc;
+    P->lp_RB = (int)RB;
+    P->lp_CW = CW;
+}
 
 bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P) {
     if (m < 1 || n < 1 || d_max < 1) return false;
@@ -108,6 +157,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->rf_grid = (int)cdiv(n, 256);
 
     P->ntickets = (int)std::max<int64_t>(P->up_ncb + 1, P->cg_ngroups + 1) + 8;
+    plan_loop(P);
 
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -143,8 +193,35 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
         std::max<size_t>(((size_t)P->up_SG + kp_max + 1) * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
     P->o_l2 = take(8 * l2_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * n);
+    if (P->loop) {
+        P->o_lp_bv = take(8 * 2 * (size_t)P->lp_G);
+        P->o_lp_bi = take(8 * 2 * (size_t)P->lp_G);
+        P->o_lp_bc = take(8 * 2 * (size_t)P->lp_G);
+        P->o_lp_part = take(8 * (size_t)P->lp_Gc * (P->D + 1));
+    }
     P->total = o;
     return true;
+}
+
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static std::mutex mu;
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        cus[dev] = v;
+    }
+    return cus[dev];
 }
 
 // Passes over Y(:, 0:d) use non-temporal loads once that read exceeds the
@@ -389,6 +466,25 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     init_state_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(P.ntickets, 256))), 256, 0, s>>>(st, tickets,
                                                                                               P.ntickets, P.D);
     RBD_LAUNCH_CHECK();
+    if (!W && P.loop && P.lp_G <= device_cus()) {
+        // the whole loop in one launch; the last two tickets (zeroed above)
+        // are its barrier counter and abort flag
+        LoopWs lw;
+        lw.bar = tickets + P.ntickets - 2;
+        lw.abort_flag = reinterpret_cast<int*>(tickets + P.ntickets - 1);
+        lw.part = reinterpret_cast<double*>(ws + P.o_lp_part);
+        lw.v1 = v1;
+        lw.bval = reinterpret_cast<double*>(ws + P.o_lp_bv);
+        lw.bidx = reinterpret_cast<int64_t*>(ws + P.o_lp_bi);
+        lw.bcnt = reinterpret_cast<double*>(ws + P.o_lp_bc);
+        LoopOut lo{Y, T, pivots, col_err, err_hist, d_out, status, stop_reason};
+        prof_begin(RBD_PHASE_LOOP, s);
+        loop_kernel<Tx><<<P.lp_G, kLoopThreads, 0, s>>>(X, ldx, (int)P.m, (int)P.n, P.D, P.d_max, tol, rel, start, lo,
+                                                        lw, P.lp_Gc, P.lp_RB, P.lp_CW);
+        RBD_LAUNCH_CHECK();
+        prof_end(RBD_PHASE_LOOP, s);
+        return RBD_OK;
+    }
     // pre-computation of diag(X'X) (section 3.3): e_j^2 = ||x_j||^2, E_0, first column
     prof_begin(RBD_PHASE_COLNORM, s);
     if (W) launch_xscan<Tx, kScanSqrW>(P, X, ldx, w, st, Y, 0, part, vec_ok, nt, s);

@@ -6,7 +6,8 @@ BF16, tol 0, d_max 512.
 The stored values are regenerated on the host in row blocks exactly as the
 device holds them (``synth.ParametricField.rows`` then ``synth.quantize``), and
 G is accumulated in FP64.  G squares the condition number, so only the steps
-whose largest error is at least 1e-6 of E_0 are written (the tests compare
+whose largest error is at least 1e-6 of E_0 are written, with the first 128
+rows of T on 32 sampled columns and the pivot columns (the tests compare
 those above 1e-5 of E_0, where the route agrees with the definitional oracle
 to about 1e-9 E_0 on reduced grids).
 
@@ -32,7 +33,8 @@ OUT = os.path.join(ROOT, "tests", "golden", "parametric_1048576x4096_gram.json")
 DTYPES = ("f32", "bf16")
 D_MAX = 512
 KEEP_FLOOR = 1e-6          # rows of the result written: E_k >= KEEP_FLOOR * E_0
-SAMPLE_COLS = 64
+SAMPLE_COLS = 32
+T_ROWS = 128             # rows of T written, on the sampled and the pivot columns
 BLOCK = 16384
 
 
@@ -59,7 +61,8 @@ def main():
         fit = oracle.rbd_fit_gram(G[dt], 0.0, D_MAX, pf.m)
         E0 = float(fit.err_hist[0])
         K = next((k for k in range(fit.d) if fit.err_hist[k] < KEEP_FLOOR * E0), fit.d)
-        cols = np.unique(np.concatenate([J, fit.pivots[:K]]))
+        Kt = min(K, T_ROWS)
+        cols = np.unique(np.concatenate([J, fit.pivots[:Kt]]))
         out["results"][dt] = dict(
             E0=E0, steps=int(K), stop_of_full_run=fit.stop, d_of_full_run=int(fit.d),
             pivots=fit.pivots[:K].tolist(),
@@ -67,7 +70,8 @@ def main():
             gap_hist=[float(g) if np.isfinite(g) else None for g in fit.gap_hist[:K + 1]],
             nu=fit.nu[:K].tolist(),
             T_cols=cols.tolist(),
-            T=fit.T[:K][:, cols].tolist(),
+            T_rows=int(Kt),
+            T=fit.T[:Kt][:, cols].tolist(),
             col_norm=np.sqrt(np.diag(G[dt])[cols]).tolist())
         print(f"{dt}: E0 = {E0:.6e}, {K} steps above {KEEP_FLOOR:g} E0", flush=True)
     with open(OUT, "w") as f:

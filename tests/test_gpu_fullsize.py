@@ -1,16 +1,58 @@
 """Parity at full size, in the launch configuration bench.py times: the parametric
 field 1,048,576 x 4096, tol 0, d_max 512, FP32 and BF16 storage.
 
-The oracle cannot run at this size, so the checks use outputs the host can form
-one at a time (T and the residual norms of sampled columns, whose stored values
-the host regenerates bit for bit) and properties that hold at any size
+The definitional oracle cannot run at this size.  The Gram-route oracle
+(Algorithm 1 through G = X'X and eq. (3)) can, on the host: its pivots, error
+history and rows of T for these exact stored values are in
+tests/golden/parametric_1048576x4096_gram.json (written by
+tests/golden/make_parametric_gram.py), trustworthy while the largest error is
+above 1e-5 of E_0.  On the steps where its two largest errors differ by more
+than 1e-7 E_0 the device must take the same pivots, with the error history and
+the rows of T agreeing to 1e-5; the error history must agree to 1e-5 E_0 on
+every step the Gram route resolves.  The other checks use outputs the host can
+form one at a time (T and the residual norms of sampled columns, whose stored
+values the host regenerates bit for bit) and properties that hold at any size
 (orthonormality of sampled basis pairs, T(:, pivots) upper triangular with
 diagonal E_{k-1}, distinct pivots, non-increasing history).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "parametric_1048576x4096_gram.json")
+
+
+def compare_with_gram_oracle(dtype, piv, hist, T, floor=1e-5, gap=1e-7, rtol=1e-5):
+    """Returns (messages, steps compared pivot by pivot, steps of history compared)."""
+    with open(GOLDEN) as f:
+        g = json.load(f)["results"][dtype]
+    E0 = g["E0"]
+    eh = np.array(g["err_hist"])
+    gh = np.array([np.inf if v is None else v for v in g["gap_hist"]])
+    steps = g["steps"]
+    msgs = []
+    if abs(hist[0] - E0) > 1e-12 * E0:
+        msgs.append(f"E_0 {hist[0]!r} vs the oracle's {E0!r}")
+    resolved = next((k for k in range(steps + 1) if eh[k] < floor * E0), steps + 1)
+    K = next((k for k in range(min(steps, resolved)) if gh[k] <= gap), min(steps, resolved))
+    if not np.array_equal(piv[:K], np.array(g["pivots"][:K])):
+        first = int(np.argmax(piv[:K] != np.array(g["pivots"][:K])))
+        msgs.append(f"pivot {first} differs from the Gram-route oracle's")
+        return msgs, K, resolved
+    dh = np.max(np.abs(hist[:resolved] - eh[:resolved]))
+    if dh > rtol * E0:
+        msgs.append(f"error history differs from the oracle's by {dh / E0:.2e} E0")
+    Kt = min(K, g["T_rows"])
+    cols = np.array(g["T_cols"])
+    Tg = np.array(g["T"])[:Kt]
+    dT = np.linalg.norm(T[:Kt][:, cols] - Tg, axis=0) / np.array(g["col_norm"])
+    if np.max(dT) > rtol:
+        msgs.append(f"rows of T differ from the oracle's by {np.max(dT):.2e} of ||x_j||")
+    return msgs, K, resolved
 
 pytestmark = pytest.mark.gpu
 
@@ -34,6 +76,10 @@ def test_parametric_field_full_size(dtype):
     col_err = res.col_err.cpu().numpy()
     T = res.T.cpu().numpy()
     E0 = hist[0]
+    msgs, K, resolved = compare_with_gram_oracle(dtype, piv, hist, T)
+    print(f"[gpu] Gram-route oracle: {K} pivots compared, error history compared on {resolved} steps", flush=True)
+    assert msgs == [], "; ".join(msgs)
+    assert K >= 40
     assert len(set(piv.tolist())) == 512
     assert np.all(np.diff(hist) <= 1e-9 * E0)
     # T(:, pivots) is upper triangular with diagonal E_{k-1}

@@ -25,11 +25,19 @@ def _same(a, b):
     return True
 
 
+@pytest.fixture(params=["auto", "0"])
+def driver(request, monkeypatch):
+    """auto: the persistent loop takes these cache-resident shapes; 0: one launch per kernel."""
+    if request.param == "0":
+        monkeypatch.setenv("RBD_LOOP", "0")
+    return request.param
+
+
 @pytest.mark.parametrize("dtype,weighted", [("f32", False), ("bf16", False), ("f32", True)])
-def test_replays_equal_eager_fits(dtype, weighted):
+def test_replays_equal_eager_fits(dtype, weighted, driver):
     import torch
     import paper_1503_05947_amd as rbd
-    print(f"[gpu] graph replay dtype={dtype} weighted={weighted}", flush=True)
+    print(f"[gpu] graph replay dtype={dtype} weighted={weighted} driver={driver}", flush=True)
     wl = synth.lowrank_spectrum(0)
     stored, _ = synth.quantize(wl.X, dtype)
     X = to_device(stored, dtype)
@@ -54,9 +62,9 @@ def test_replays_equal_eager_fits(dtype, weighted):
     g.close()
 
 
-def test_fixed_steps_bump_field_replay():
+def test_fixed_steps_bump_field_replay(driver):
     import paper_1503_05947_amd as rbd
-    print("[gpu] graph replay bump field 2048 x 2048 fixed 256 steps", flush=True)
+    print(f"[gpu] graph replay bump field 2048 x 2048 fixed 256 steps driver={driver}", flush=True)
     wl = synth.bump_field(0)
     X = to_device(synth.quantize(wl.X, "f32")[0], "f32")
     eager = _snap(rbd.fit(X, tol=0.0, d_max=256))

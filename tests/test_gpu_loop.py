@@ -1,0 +1,127 @@
+"""The persistent greedy loop (one launch for the whole of Algorithm 1 on a
+cache-resident X) against the FP64 oracle, and against the one-launch-per-
+kernel driver on the same inputs.  RBD_LOOP=1 forces the persistent loop
+wherever the shape allows it, RBD_LOOP=0 turns it off.  Every case prints its
+name, shape and driver before touching the GPU."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import compare_fit
+from test_gpu_fit import run_fit, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def fit_with(monkeypatch, loop, stored, dtype, tol, d_max, rel=False, start=-1, pad_cols=0):
+    monkeypatch.setenv("RBD_LOOP", loop)
+    return run_fit(stored, dtype, tol, d_max, rel=rel, start=start, pad_cols=pad_cols)
+
+
+def check_both(monkeypatch, name, stored, vals, dtype, tol, d_max, rel=False, start=-1, pad_cols=0,
+               exact_d=True):
+    ref = oracle.rbd_fit(vals, tol, d_max, rel=rel, start=start)
+    out = {}
+    for loop in ("1", "0"):
+        print(f"[gpu] loop {name} dtype={dtype} shape={vals.shape} tol={tol} rel={rel} d_max={d_max} "
+              f"RBD_LOOP={loop}", flush=True)
+        dev = fit_with(monkeypatch, loop, stored, dtype, tol, d_max, rel=rel, start=start, pad_cols=pad_cols)
+        rep = compare_fit(dev, ref, vals, exact_d=exact_d)
+        print(f"[gpu]   {rep.summary()}", flush=True)
+        assert rep == [], f"{name} RBD_LOOP={loop}: " + "; ".join(rep)
+        out[loop] = dev
+    return out["1"], out["0"], ref
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+def test_lowrank_both_drivers(dtype, monkeypatch):
+    w = synth.lowrank_spectrum(1)
+    stored, vals = synth.quantize(w.X, dtype)
+    a, b, ref = check_both(monkeypatch, "lowrank", stored, vals, dtype, w.tol, w.d_max)
+    assert a["d"] == b["d"] == ref.d and a["stop"] == b["stop"] == ref.stop
+    if dtype == "f64":
+        assert np.array_equal(a["pivots"], ref.pivots)
+
+
+def test_bump_field_tolerance_and_fixed(monkeypatch):
+    w = synth.bump_field(0)
+    stored, vals = synth.quantize(w.X, "f32")
+    a, b, ref = check_both(monkeypatch, "bump 2048^2 rel 1e-4", stored, vals, "f32", w.tol, w.d_max, rel=True)
+    assert a["stop"] == "tol" and a["d"] == ref.d
+    a, b, ref = check_both(monkeypatch, "bump 2048^2 fixed", stored, vals, "f32", 0.0, 256, exact_d=False)
+    assert a["d"] == 256 and a["stop"] == "dmax"
+
+
+def test_bump_field_f64_exact_pivots_persistent(monkeypatch):
+    w = synth.bump_field(0)
+    stored, vals = synth.quantize(w.X, "f64")
+    print("[gpu] loop bump 2048^2 f64 RBD_LOOP=1", flush=True)
+    dev = fit_with(monkeypatch, "1", stored, "f64", w.tol, w.d_max, rel=True)
+    ref = oracle.rbd_fit(vals, w.tol, w.d_max, rel=True)
+    assert compare_fit(dev, ref, vals) == []
+    assert dev["d"] == ref.d and np.array_equal(dev["pivots"], ref.pivots)
+
+
+@pytest.mark.parametrize("m,n,dtype,d_max", [(1111, 777, "bf16", 100), (300, 5000, "f32", 60),
+                                             (70000, 40, "f32", 40), (64, 64, "f64", 64), (5, 3000, "f32", 5)])
+def test_ragged_shapes(m, n, dtype, d_max, monkeypatch):
+    """Column slices that do not divide n, one column per workgroup, Gram-Schmidt
+    row blocks that do not divide m, d reaching min(m, n)."""
+    w = synth.bump_field(11, m=m, n=n)
+    stored, vals = synth.quantize(w.X, dtype)
+    check_both(monkeypatch, f"ragged {m}x{n}", stored, vals, dtype, 0.0, d_max, exact_d=False)
+
+
+def test_layouts_and_starts(monkeypatch):
+    w = synth.bump_field(3, m=300, n=257)
+    stored, vals = synth.quantize(w.X, "f32")
+    check_both(monkeypatch, "ldx = n + 3", stored, vals, "f32", 1e-3, 60, rel=True, pad_cols=3)
+    check_both(monkeypatch, "start = 200", stored, vals, "f32", 0.0, 30, start=200, exact_d=False)
+
+
+def test_edge_cases(monkeypatch):
+    monkeypatch.setenv("RBD_LOOP", "1")
+    print("[gpu] loop edge cases RBD_LOOP=1", flush=True)
+    dev = run_fit(np.zeros((33, 17), np.float32), "f32", 0.0, 5)
+    assert dev["d"] == 0 and dev["stop"] == "break" and dev["err_hist"].tolist() == [0.0]
+    X = synth.rng(97, 0, 0).standard_normal((30, 20))
+    E0 = np.linalg.norm(X, axis=0).max()
+    dev = run_fit(X, "f64", E0 * 1.001, 10)
+    assert dev["d"] == 0 and dev["stop"] == "break"
+    dev = run_fit(X, "f64", E0, 10)
+    assert dev["d"] == 1 and dev["stop"] == "tol"
+    dev = run_fit(np.array([[3.0, -4.0, 1.0]]), "f64", 0.0, 3)
+    assert dev["d"] == 1 and dev["pivots"].tolist() == [1] and abs(dev["T"][0, 1] - 4.0) < 1e-15
+    dev = run_fit(np.array([[3.0], [4.0]]), "f64", 0.0, 3)
+    assert dev["d"] == 1 and abs(dev["err_hist"][0] - 5.0) < 1e-15 and dev["err_hist"][1] == 0.0
+    X = synth.rng(97, 1, 0).standard_normal((20, 8))
+    X[:, 5] = X[:, 2] = X[:, 2] * 10.0
+    dev = run_fit(X, "f64", 1e-12, 8)
+    assert dev["pivots"][0] == 2 and 5 not in dev["pivots"].tolist() and dev["d"] == 7
+    for k in (1, 5, 17):
+        Xr = synth.random_rank(k, 640, 300, k)
+        dev = run_fit(Xr, "f64", 1e-10, 64, rel=True)
+        assert dev["d"] == k and dev["stop"] == "tol"
+
+
+def test_nonfinite_input(monkeypatch):
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    monkeypatch.setenv("RBD_LOOP", "1")
+    print("[gpu] loop nonfinite RBD_LOOP=1", flush=True)
+    X = torch.ones((40, 30), dtype=torch.float32)
+    X[7, 3] = float("nan")
+    with pytest.raises(FloatingPointError):
+        rbd.fit(X.cuda(), tol=0.0, d_max=4)
+
+
+def test_bitwise_deterministic(monkeypatch):
+    w = synth.bump_field(4, m=700, n=900)
+    stored, vals = synth.quantize(w.X, "f32")
+    print("[gpu] loop determinism RBD_LOOP=1", flush=True)
+    a = fit_with(monkeypatch, "1", stored, "f32", 0.0, 64)
+    b = fit_with(monkeypatch, "1", stored, "f32", 0.0, 64)
+    for key in ("Y", "T", "pivots", "col_err", "err_hist"):
+        assert np.array_equal(a[key], b[key]), key

@@ -28,10 +28,13 @@ def gauss():
     return synth.quantize(g.standard_normal((M, N)), "f32")
 
 
-def test_identity_at_max_d(gauss):
+@pytest.mark.parametrize("loop", ["0", "1"])
+def test_identity_at_max_d(gauss, loop, monkeypatch):
+    """loop = 0: one launch per kernel of a step; 1: the persistent loop."""
     import paper_1503_05947_amd as rbd
+    monkeypatch.setenv("RBD_LOOP", loop)
     stored, vals = gauss
-    print(f"[gpu] max d identity {M}x{N} d_max={D}", flush=True)
+    print(f"[gpu] max d identity {M}x{N} d_max={D} RBD_LOOP={loop}", flush=True)
     dev = _host(rbd.fit(to_device(stored, "f32"), tol=0.0, d_max=D))
     ref = oracle.rbd_fit(vals, 0.0, D)
     assert dev["d"] == D == ref.d

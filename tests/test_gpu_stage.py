@@ -21,6 +21,13 @@ def _host(res):
                 col_err=res.col_err.cpu().numpy(), err_hist=res.err_hist.cpu().numpy(), d=res.d, stop=res.stop)
 
 
+@pytest.fixture(autouse=True)
+def multi_launch_driver(monkeypatch):
+    """These cases check the staged basis columns of the one-launch-per-kernel
+    driver; the persistent loop would otherwise take shapes this small."""
+    monkeypatch.setenv("RBD_LOOP", "0")
+
+
 @pytest.fixture(scope="module")
 def field():
     g = synth.rng(95, 0, 0)
