@@ -196,10 +196,11 @@ int rbd_fit_graph_destroy(rbd_fit_graph graph);
  * row range outside [0, a_nnz) or a decreasing a_indptr is reported through
  * *status as RBD_EMATRIX (d = 0), and no kernel reads outside the arrays.
  * The errors are downdated as for a diagonal A with g = (I - YY')(A xi)
- * (two sparse products per step).  Unlike rbd_fit, this entry point
- * synchronises its stream once per greedy step: exact refreshes of queued
- * columns materialise their residuals in chunks, and the host reads the
- * queue length to launch them.  Other arguments, outputs and errors are
+ * (two sparse products per step).  Exact refreshes of queued columns
+ * materialise their residuals in chunks of columns: every step enqueues the
+ * chunks for the longest possible queue, and each chunk reads the queue's
+ * length on the device (empty chunks return at once), so, as rbd_fit, the
+ * call never waits for the device.  Other arguments, outputs and errors are
  * those of rbd_fit; workspace: rbd_fit_spd_workspace_size() bytes.
  */
 int rbd_fit_spd_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, size_t* bytes);
@@ -398,6 +399,17 @@ enum {
 int rbd_profiler_begin(uint32_t phase_mask);
 int rbd_profiler_end(double* phase_ms, int64_t* phase_launches, int32_t nphase,
                      double* step_end_ms, int64_t nstep, int64_t* nstep_out);
+
+/*
+ * rbd_read_stream -- a measurement tool: reads `bytes` of device memory at
+ * `data` once with the X-scan's 16-byte loads (non-temporal when
+ * `nontemporal` is nonzero, as the scan uses them for X above 512 MB) and
+ * discards the values, so the time it takes gives the read bandwidth a scan of
+ * that buffer can reach.  `sink` is 4 bytes of device memory that the kernel
+ * may write.  `data` must be 16-byte aligned and `bytes` a multiple of 16.
+ * Returns RBD_OK, RBD_EINVAL or RBD_EDEVICE.
+ */
+int rbd_read_stream(const void* data, size_t bytes, int nontemporal, void* sink, void* stream);
 
 /* Human-readable text for a return or status code (static storage). */
 const char* rbd_status_string(int code);

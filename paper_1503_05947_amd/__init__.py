@@ -126,7 +126,7 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
              weights=None, A: "CsrMatrix | None" = None) -> None:
     """Enqueue rbd_fit (rbd_fit_weighted when ``weights`` is given: A = diag(weights);
     rbd_fit_spd when a CsrMatrix ``A`` is given) on ``stream`` (default: torch's
-    current stream).  Only the SPD variant waits (once per greedy step)."""
+    current stream).  None of the variants waits for the device."""
     torch = _torch()
     _check_matrix(X, "X")
     if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
@@ -252,6 +252,20 @@ def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1
     fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream, weights=weights, A=A)
     (stream or torch.cuda.current_stream(X.device)).synchronize()
     return bufs.result()
+
+
+def read_stream(t, nontemporal: bool = True, stream=None) -> None:
+    """Enqueue rbd_read_stream over a contiguous device tensor (a measurement tool:
+    one read of every byte, the values discarded)."""
+    torch = _torch()
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("read_stream needs a contiguous device tensor")
+    sink = torch.empty(1, dtype=torch.int32, device=t.device)
+    with torch.cuda.device(t.device):
+        s = stream if stream is not None else torch.cuda.current_stream(t.device)
+        rc = load().rbd_read_stream(t.data_ptr(), t.numel() * t.element_size(), int(bool(nontemporal)),
+                                    sink.data_ptr(), s.cuda_stream)
+    _lib.check(rc, "rbd_read_stream")
 
 
 def project(Y, V, stream=None):

@@ -54,6 +54,7 @@ SIGNATURES = {
                                                 _i64, _vp, _i64, _i64, _i32, _vp, _i64, _vp, _sz, _vp]),
     "rbd_profiler_begin": (ctypes.c_int, [ctypes.c_uint32]),
     "rbd_profiler_end": (ctypes.c_int, [_vp, _vp, _i32, _vp, _i64, _vp]),
+    "rbd_read_stream": (ctypes.c_int, [_vp, _sz, ctypes.c_int, _vp, _vp]),
     "rbd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rbd_version": (ctypes.c_char_p, []),
 }

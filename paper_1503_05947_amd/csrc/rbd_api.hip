@@ -6,8 +6,6 @@
 // one step with d = s (the device keeps the real d, and every kernel returns
 // at once after the stop flag is set).  The host therefore knows an upper
 // bound of d for each launch and sizes register tiles (KC) from it.
-// rbd_fit_spd is the exception: it reads the loop state once per step to size
-// its exact refreshes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -480,7 +478,7 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         LoopOut lo{Y, T, pivots, col_err, err_hist, d_out, status, stop_reason};
         prof_begin(RBD_PHASE_LOOP, s);
         loop_kernel<Tx><<<P.lp_G, kLoopThreads, 0, s>>>(X, ldx, (int)P.m, (int)P.n, P.D, P.d_max, tol, rel, start, lo,
-                                                        lw, P.lp_Gc, P.lp_RB, P.lp_CW);
+                                                        lw, P.lp_Gc, P.lp_RB, P.lp_CW, vec_ok);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_LOOP, s);
         return RBD_OK;
@@ -791,34 +789,29 @@ int fit_spd_typed(const SpdPlan& Q, const Tx* X, int64_t ldx, Csr A, double tol,
                                                        bres_v, bres_i, pivots, err_hist, start, tol, rel);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_UPDATE, s);
-        // the number of queued columns decides the refresh launches
-        State h;
-        if (hipMemcpyAsync(&h, st, sizeof(State), hipMemcpyDeviceToHost, s) != hipSuccess) return RBD_EDEVICE;
-        if (hipStreamSynchronize(s) != hipSuccess) return RBD_EDEVICE;
-        if (h.stop) break;
+        // exact refreshes: chunks for every possible queue length, each sized on
+        // the device from the queue's length (an empty chunk, or a step with
+        // nothing queued, or a step after the loop has stopped, costs one empty
+        // launch per kernel), so the host never waits
         prof_begin(RBD_PHASE_RESID, s);
-        if (h.nflag > 0) {
-            launch_ys_flush<false>(P, Y, st, d + 1, ys, s);
+        launch_ys_flush<false>(P, Y, st, d + 1, ys, s);
+        RBD_LAUNCH_CHECK();
+        for (int c0 = 0; c0 < P.n; c0 += Q.cq) {
+            const int cc = (int)std::min<int64_t>(Q.cq, P.n - c0);      // at most this many queued columns
+            const unsigned grid = (unsigned)std::min<int64_t>(2048, cdiv(cc, 64) * P.rc_S);
+            resid_mfma_kernel<Tx, true><<<grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist + c0,
+                                                              &st->nflag, 0, P.rc_rows, P.rc_S, nullptr, 0, nullptr,
+                                                              rbuf, Q.cq, c0, Q.cq);
             RBD_LAUNCH_CHECK();
-            for (int c0 = 0; c0 < h.nflag; c0 += Q.cq) {
-                const int cc = std::min(Q.cq, h.nflag - c0);
-                const unsigned grid = (unsigned)std::min<int64_t>(2048, cdiv(cc, 64) * P.rc_S);
-                resid_mfma_kernel<Tx, true><<<grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist + c0,
-                                                                  nullptr, cc, P.rc_rows, P.rc_S, nullptr, 0, nullptr,
-                                                                  rbuf, Q.cq);
-                RBD_LAUNCH_CHECK();
-                csr_quad_kernel<<<dim3((unsigned)cdiv(cc, 64), (unsigned)Q.q_S), 64 * kQuadGroups, 0, s>>>(
-                    rbuf, Q.cq, P.m, cc, A, Q.q_rows, qpart, P.n, c0);
-                RBD_LAUNCH_CHECK();
-            }
+            csr_quad_kernel<<<dim3((unsigned)cdiv(cc, 64), (unsigned)Q.q_S), 64 * kQuadGroups, 0, s>>>(
+                rbuf, Q.cq, P.m, &st->nflag, Q.cq, A, Q.q_rows, qpart, P.n, c0);
+            RBD_LAUNCH_CHECK();
         }
         prof_end(RBD_PHASE_RESID, s);
         prof_begin(RBD_PHASE_RESID_FINISH, s);
-        if (h.nflag > 0) {
-            resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, qpart, P.n, Q.q_S, flist, e2, base2, P.n, tickets,
-                                                          pivots, err_hist, d);
-            RBD_LAUNCH_CHECK();
-        }
+        resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, qpart, P.n, Q.q_S, flist, e2, base2, P.n, tickets,
+                                                      pivots, err_hist, d);
+        RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID_FINISH, s);
         prof_step(s);
     }
@@ -1184,6 +1177,20 @@ int rbd_profiler_end(double* phase_ms, int64_t* phase_launches, int32_t nphase, 
     g_prof.used = 0;
     g_prof.marks.clear();
     g_prof.steps.clear();
+    return RBD_OK;
+}
+
+int rbd_read_stream(const void* data, size_t bytes, int nontemporal, void* sink, void* stream) {
+    if (!data || !sink || bytes == 0 || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(data) % 16 != 0)
+        return RBD_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t nvec = (int64_t)(bytes / 16);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, cdiv(nvec, 256)));
+    const u32x4* v = reinterpret_cast<const u32x4*>(data);
+    unsigned* out = reinterpret_cast<unsigned*>(sink);
+    if (nontemporal) read_stream_kernel<true><<<grid, 256, 0, s>>>(v, nvec, 0x9e3779b9u, out);
+    else read_stream_kernel<false><<<grid, 256, 0, s>>>(v, nvec, 0x9e3779b9u, out);
+    RBD_LAUNCH_CHECK();
     return RBD_OK;
 }
 

@@ -214,6 +214,37 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
 }
 
 // ---------------------------------------------------------------------------
+// read_stream: every 16-byte vector of a buffer read once (the X-scan's loads,
+// non-temporal when NT), values folded into a register and discarded.  The
+// bandwidth a scan of that buffer can reach.  Workgroups own contiguous
+// chunks; eight loads in flight per thread.
+// ---------------------------------------------------------------------------
+template <bool NT>
+__global__ __launch_bounds__(256) void read_stream_kernel(const u32x4* __restrict__ v, int64_t nvec,
+                                                          unsigned key, unsigned* __restrict__ sink) {
+    const int64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per, b = min(nvec, a + per);
+    unsigned acc = 0u;
+    constexpr int U = 8;
+    int64_t i = a + threadIdx.x;
+    for (; i + (U - 1) * (int64_t)blockDim.x < b; i += U * (int64_t)blockDim.x) {
+        u32x4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const u32x4* q = v + i + u * (int64_t)blockDim.x;
+            r[u] = NT ? __builtin_nontemporal_load(q) : *q;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc ^= r[u].x ^ r[u].y ^ r[u].z ^ r[u].w;
+    }
+    for (; i < b; i += blockDim.x) {
+        const u32x4 r = v[i];
+        acc ^= r.x ^ r.y ^ r.z ^ r.w;
+    }
+    if (acc == key) *sink = acc;     // keeps the loads; practically never taken
+}
+
+// ---------------------------------------------------------------------------
 // update: finish the column sums (slab groups, fixed order), then either
 // initialise the errors (INIT) or downdate them (STEP), and take the
 // lowest-index argmax.  One block per 256 columns; the last block to arrive
@@ -1100,9 +1131,11 @@ __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(c
                                                           const int* __restrict__ count_dev, int count_host,
                                                           int rows_per_slab, int nslab, double* __restrict__ part,
                                                           int64_t ldp, const double* __restrict__ w,
-                                                          double* __restrict__ R = nullptr, int64_t ldr = 0) {
-    const int cnt = count_dev ? *count_dev : count_host;
-    if (cnt == 0) return;
+                                                          double* __restrict__ R = nullptr, int64_t ldr = 0,
+                                                          int count_off = 0, int count_cap = INT32_MAX) {
+    // the queue entries [count_off, count_off + count_cap) of a device-side count
+    const int cnt = count_dev ? min(max(*count_dev - count_off, 0), count_cap) : count_host;
+    if (cnt <= 0) return;
     constexpr int TM = 128, TN = 64, KB = 16;
     constexpr int YQ = TM * KB / 256, CQ = KB * TN / 256;
     __shared__ double Ys[TM][KB + 1];
@@ -1368,8 +1401,12 @@ __global__ __launch_bounds__(256) void spmv_kernel(const State* __restrict__ st,
 constexpr int kQuadGroups = 4;
 constexpr int kQuadChunk = 2048;
 __global__ __launch_bounds__(64 * kQuadGroups) void csr_quad_kernel(const double* __restrict__ R, int64_t ldr, int64_t m,
-                                                                    int cnt, Csr A, int rows_per_slab,
-                                                                    double* __restrict__ part, int64_t ldp, int c0) {
+                                                                    const int* __restrict__ count_dev, int cap, Csr A,
+                                                                    int rows_per_slab, double* __restrict__ part,
+                                                                    int64_t ldp, int c0) {
+    // the chunk holds queue entries [c0, c0 + cnt): cnt from the device-side queue length
+    const int cnt = min(max(*count_dev - c0, 0), cap);
+    if (blockIdx.x * 64 >= cnt) return;
     __shared__ int s_row[kQuadChunk];
     __shared__ int s_col[kQuadChunk];
     __shared__ double s_val[kQuadChunk];

@@ -173,6 +173,43 @@ def bump_field(seed: int = 0, m: int = 2048, n: int = 2048, noise: float = 1e-4,
                     meta=dict(m=m, n=n, bumps=len(amps)))
 
 
+def bump_fill(seed: int, out, noise: float = 1e-4, cfg: int = 2, rows_per_chunk: int = 8192) -> None:
+    """Write the stored values of ``bump_field(seed, m, n, noise)`` into a torch tensor
+    ``out`` (m x n, float64/float32/bfloat16, any device).
+
+    The same FP64 products and sums in the same order as ``bump_field`` (so the
+    values are bit-identical to the host's), then one rounding to the storage
+    type; the noise is drawn on the host from the same stream.  This is input
+    generation, not part of the decomposition.
+    """
+    import torch
+
+    m, n = out.shape
+    centres, widths, amps = bump_params(seed, cfg=cfg)
+    s1 = np.arange(m, dtype=np.float64) / max(m - 1, 1)
+    s2 = np.arange(n, dtype=np.float64) / max(n - 1, 1)
+    ag1 = np.stack([a * np.exp(-((s1 - c1) ** 2) / (2.0 * w * w)) for (c1, _), w, a in zip(centres, widths, amps)])
+    g2 = np.stack([np.exp(-((s2 - c2) ** 2) / (2.0 * w * w)) for (_, c2), w in zip(centres, widths)])
+    dev = out.device
+    A = torch.from_numpy(ag1).to(dev)
+    B = torch.from_numpy(g2).to(dev)
+    g = rng(cfg, seed, S_NOISE) if noise else None
+    for r0 in range(0, m, rows_per_chunk):
+        r1 = min(m, r0 + rows_per_chunk)
+        acc = torch.zeros((r1 - r0, n), dtype=torch.float64, device=dev)
+        for b in range(A.shape[0]):
+            acc += A[b, r0:r1, None] * B[b, None, :]
+        if g is not None:
+            acc += noise * torch.from_numpy(g.standard_normal((r1 - r0, n))).to(dev)
+        if out.dtype == torch.float64:
+            out[r0:r1] = acc
+        elif out.dtype == torch.float32:
+            out[r0:r1] = acc.to(torch.float32)
+        else:
+            out[r0:r1] = acc.to(torch.float32).to(out.dtype)
+        del acc
+
+
 # ----------------------------------------------------------------------------
 # 3. parametric field (1,048,576 x 4096 at full size)
 # ----------------------------------------------------------------------------
