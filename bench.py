@@ -47,15 +47,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="extra profiled fit with a per-phase breakdown")
     ap.add_argument("--sample-cols", type=int, default=64)
-    ap.add_argument("--batched", action="store_true",
-                    help="also time the batched fit: 4096 matrices, m, n log-uniform in [64, 1024], "
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the batched, backward and recognition sections (all three run by default)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched fit: 4096 matrices, m, n log-uniform in [64, 1024], "
                          "spectrum 10^(-i/8), FP32, relative tol 1e-6")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--backward", action="store_true",
-                    help="also time the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
                          "fixed from a tol-0 fit, G ~ N(0,1)")
-    ap.add_argument("--classify", action="store_true",
-                    help="also time recognition of 262144 generated queries in compressed coordinates")
+    ap.add_argument("--no-classify", action="store_true",
+                    help="skip recognition of 262144 generated queries in compressed coordinates")
     ap.add_argument("--spd", action="store_true",
                     help="also time the general SPD A-norm fit (A = I + grid Laplacian) on the FP32 field")
     ap.add_argument("--weighted", action="store_true",
@@ -205,8 +207,12 @@ def equal_error_report(runs, pf, ncols):
         entry = {"E0_stored": E0, "sampled_rel_err": [s / nx64.max() for s in sampled],
                  "certified_rel_err_at_checkpoints": [cert[k] for k in ds], "time_to_eps_ms": {}}
         entry["time_to_eps_sampled_ms"] = {}
+        # the certified bound cannot go below twice its storage term: at smaller eps
+        # the storage type is not certifiable (null), whatever the fit reaches
+        floor = 2.0 * q / E0_64_bound
+        entry["certifiable_down_to"] = floor
         for eps in EPS_BOTH + (EPS_FP32 if name == "f32" else ()):
-            dd = next((k for k in range(1, d + 1) if cert[k] <= eps), None)
+            dd = next((k for k in range(1, d + 1) if cert[k] <= eps), None) if eps >= floor else None
             entry["time_to_eps_ms"][f"{eps:g}"] = (
                 None if dd is None else {"d": dd, "ms": round(steps[dd - 1], 3) if dd - 1 < len(steps) else None})
             ds_ok = [k for k, e in zip(ds, entry["sampled_rel_err"]) if e <= eps]
@@ -224,10 +230,12 @@ def equal_error_report(runs, pf, ncols):
                 ratio[f"{eps:g}"] = (round(a32["ms"] / a16["ms"], 3)
                                      if a32 and a16 and a32["ms"] and a16["ms"] else None)
             report[out] = ratio
+        report["time_fp32_over_bf16"] = report["time_fp32_over_bf16_sampled"]
     report["note"] = ("certified: (E_d of the stored matrix + storage unit roundoff * max ||x||) / max ||x64||, "
-                      "an upper bound on max_j ||x64_j - Y T_j|| / max_j ||x64_j|| at every d; sampled: the same "
-                      "quantity evaluated exactly on the sampled columns at the checkpoints (a lower bound on the "
-                      "max over all columns).  Times are the fit's elapsed device time to the end of step d.")
+                      "an upper bound on max_j ||x64_j - Y T_j|| / max_j ||x64_j|| at every d, null below twice its storage "
+                      "term; sampled: the same quantity evaluated exactly on the sampled columns at the checkpoints "
+                      "(a lower bound on the max over all columns), the headline time_fp32_over_bf16.  Times are "
+                      "the fit's elapsed device time to the end of step d.")
     return report
 
 
@@ -290,33 +298,35 @@ def batched_section(rbd, count, K, W, d_max=128, tol=1e-6):
     # basis twice (Gram-Schmidt passes); the exact refreshes are not counted
     xbytes = float(np.sum(ds * ms * ns * 4))
     ybytes = float(np.sum(ms * ds * (ds - 1) * 8))           # sum over steps of 2 * m * k * 8
-    return {"matrices": count, "d_max": d_max, "tol_rel": tol, "storage": "f32",
-            "config": {"threads": cfg.threads, "wg_per_cu": cfg.wg_per_cu},
-            "autotune_ms": {f"{t}x{w}": round(v, 3) for (t, w), v in plan.trials.items()},
-            "ms_per_batch": round(sec * 1e3, 3), "matrices_per_s": round(count / sec, 1),
+    gbs = (xbytes + ybytes) / sec / 1e9
+    return {"workload": f"{count} matrices, m, n log-uniform in [64, 1024], X_b = U diag(10^(-i/8)) V', FP32, "
+                        f"relative tol {tol:g}, d_max {d_max}, one persistent launch",
+            "value": round(count / sec, 1), "unit": "matrices/s", "ms_per_batch": round(sec * 1e3, 3),
             "greedy_steps_per_s": round(float(ds.sum()) / sec, 1), "mean_d": round(float(ds.mean()), 2),
             "status_ok": int((status == 0).sum()),
-            "algorithmic_GB": round((xbytes + ybytes) / 1e9, 3),
-            "effective_GBs": round((xbytes + ybytes) / sec / 1e9, 1),
-            "note": "X_b is re-read every step; the whole batch (1.9 GB FP32) exceeds the 256 MB Infinity Cache, "
-                    "but the matrices in flight at any time fit in it, so effective bandwidth can exceed HBM's"}
+            "config": {"threads": cfg.threads, "wg_per_cu": cfg.wg_per_cu},
+            "autotune_ms": {f"{t}x{w}": round(v, 3) for (t, w), v in plan.trials.items()},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_GB": round((xbytes + ybytes) / 1e9, 3),
+                         "note": "algorithmic bytes: X_b once per greedy step plus two reads of the basis per step "
+                                 "(exact refreshes not counted); the matrices in flight fit in the 256 MB "
+                                 "Infinity Cache, so this can exceed HBM's rate"}}
 
 
-def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True):
+def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True, cpu_rows=8192):
+    """Gradient of L = <G, Y Y' X> with the pivots of a tol-0, d-step fit held fixed
+    (bump field 65536 x 2048, FP32 storage, G ~ N(0,1) in FP64): FP64 matrix-core GEMMs."""
     import numpy as np
     import torch
 
     import synth
     log(f"backward: bump field {m} x {n}, d = {d}")
-    w = synth.bump_field(0, m=m, n=n, d_max=d)
-    Xs, Xv = synth.quantize(w.X, "f32")
-    del w
     dev = torch.device("cuda:0")
-    X = torch.from_numpy(Xs).to(dev)
+    X = torch.empty((m, n), dtype=torch.float32, device=dev)
+    synth.bump_fill(0, X)
     G64 = synth.cotangent(0, m, n)
     G = torch.from_numpy(G64).to(dev)
     res = rbd.fit(X, tol=0.0, d_max=d)
-    fwd = []
     for _ in range(W):
         rbd.reconstruct_backward(X, G, res.Y, res.T, res.pivots)
     torch.cuda.synchronize()
@@ -330,11 +340,15 @@ def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True):
         Z = rbd.reconstruct(res.Y, res.T)
     torch.cuda.synchronize()
     fsec = (time.perf_counter() - t0) / K
+    del Z
     flops = 8.0 * m * n * d + 6.0 * m * d * d
-    out = {"m": m, "n": n, "d": d, "storage": "f32", "cotangent": "f64",
-           "ms": round(sec * 1e3, 3), "algorithmic_GFLOP": round(flops / 1e9, 2),
-           "TFLOPs": round(flops / sec / 1e12, 2), "peak_TFLOPs_f64_matrix": 78.6,
-           "frac": round(flops / sec / 78.6e12, 4),
+    out = {"workload": f"bump field {m} x {n} (FP32 storage), d = {d} pivots fixed from a tol-0 fit, "
+                       f"G ~ N(0,1) (FP64), L = <G, Y Y'X>",
+           "value": round(1.0 / sec, 2), "unit": "backward passes/s", "ms": round(sec * 1e3, 3),
+           "roofline": {"bound": "mfma", "achieved": round(flops / sec / 1e12, 2), "peak": 78.6,
+                        "unit": "TFLOP/s", "frac": round(flops / sec / 78.6e12, 4),
+                        "algorithmic_GFLOP": round(flops / 1e9, 2),
+                        "note": "8mnd + 6md^2 algorithmic flops, FP64 matrix cores (78.6 TFLOP/s dense FP64)"},
            "reconstruct_ms": round(fsec * 1e3, 3), "reconstruct_TFLOPs": round(2.0 * m * n * d / fsec / 1e12, 2)}
     if cpu:
         import oracle
@@ -343,10 +357,19 @@ def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True):
             cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
         except Exception:
             cores = os.cpu_count() or 1
+        Xs = X[:cpu_rows].double().cpu().numpy()
+        Gs = G64[:cpu_rows]
+        piv = res.pivots.cpu().numpy()
         t0 = time.perf_counter()
-        oracle.reconstruction_grad(Xv, res.pivots.cpu().numpy(), G64)
-        out["cpu_baseline"] = {"value_ms": round((time.perf_counter() - t0) * 1e3, 1), "cores": int(cores),
-                               "kind": "oracle", "sample": "the full-size gradient, once"}
+        oracle.reconstruction_grad(Xs, piv, Gs)
+        t = time.perf_counter() - t0
+        scale = m / cpu_rows                          # the gradient's cost is linear in m
+        out["cpu_baseline"] = {"value": round(1.0 / (t * scale), 4), "unit": "backward passes/s",
+                               "cores": int(cores), "kind": "oracle",
+                               "sample": f"the oracle gradient on rows 0..{cpu_rows - 1} of the field with the same "
+                                         f"pivots ({t:.2f} s), scaled by m / {cpu_rows} = {scale:g}"}
+    del X, G
+    torch.cuda.empty_cache()
     return out
 
 
@@ -387,9 +410,10 @@ def classify_section(rbd, K, W, k=262144, d_max=40, cpu=True):
                        f"{k} generated query views (FP32)", "d": d, "queries": k,
            "value": round(k / sec, 1), "unit": "queries/s", "ms": round(sec * 1e3, 3),
            "accuracy": round(acc, 4),
-           "projection_GFLOP": round(flops / 1e9, 1), "projection_TFLOPs": round(flops / sec / 1e12, 2),
-           "peak_TFLOPs_f64_matrix": 78.6, "frac": round(flops / sec / 78.6e12, 4),
-           "query_GB": round(m * k * 4 / 1e9, 2)}
+           "roofline": {"bound": "mfma", "achieved": round(flops / sec / 1e12, 2), "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": round(flops / sec / 78.6e12, 4), "algorithmic_GFLOP": round(flops / 1e9, 1),
+                        "note": "2 m d k flops of the projection Y'V (FP64 matrix cores); the query stream is "
+                                f"{m * k * 4 / 1e9:.2f} GB"}}
     if cpu:
         import oracle
         try:
@@ -410,43 +434,104 @@ def classify_section(rbd, K, W, k=262144, d_max=40, cpu=True):
     return out
 
 
+def _time_fit(rbd, X, tol, rel, d_max, reps, warm):
+    import torch
+    bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
+    for _ in range(max(warm, 1)):
+        rbd.fit_into(bufs, X, tol=tol, rel=rel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rbd.fit_into(bufs, X, tol=tol, rel=rel)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    d = bufs.result().d
+    return bufs, {"greedy_steps": d, "ms_per_fit": round(sec * 1e3, 4), "greedy_steps_per_s": round(d / sec, 1),
+                  "us_per_step": round(sec / max(d, 1) * 1e6, 2)}
+
+
+def _with_driver(loop, fn):
+    """Run fn() with RBD_LOOP set (None: the library's own choice)."""
+    old = os.environ.get("RBD_LOOP")
+    if loop is None:
+        os.environ.pop("RBD_LOOP", None)
+    else:
+        os.environ["RBD_LOOP"] = loop
+    try:
+        return fn()
+    finally:
+        if old is None:
+            os.environ.pop("RBD_LOOP", None)
+        else:
+            os.environ["RBD_LOOP"] = old
+
+
 def bump_field_section(rbd, K, W):
     """The 2048 x 2048 bump field (FP32), relative tol 1e-4 with d_max 256, and the
     same field in fixed-step mode (tol 0, all 256 steps): cache-resident, so the
-    step time is launch and dependency latency, not HBM bandwidth."""
+    step time is latency, not HBM bandwidth.  The library runs such fits as one
+    persistent launch; the one-launch-per-kernel driver is timed beside it."""
     import torch
 
     import synth
     wl = synth.bump_field(0)
     X = torch.from_numpy(synth.quantize(wl.X, "f32")[0]).to("cuda:0")
     out = {"workload": "bump_field 2048x2048 (50 Gaussian bumps + 1e-4 noise), FP32, d_max 256"}
+    reps = max(K, 1) * 5
     for name, tol, rel in (("rel_tol_1e-4", wl.tol, True), ("fixed_256_steps", 0.0, False)):
-        bufs = rbd.FitBuffers(2048, 2048, wl.d_max, X.dtype, X.device)
-        for _ in range(max(W, 1)):
-            rbd.fit_into(bufs, X, tol=tol, rel=rel)
-        torch.cuda.synchronize()
-        reps = max(K, 1) * 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            rbd.fit_into(bufs, X, tol=tol, rel=rel)
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / reps
-        d = bufs.result().d
-        out[name] = {"greedy_steps": d, "ms_per_fit": round(sec * 1e3, 3), "greedy_steps_per_s": round(d / sec, 1),
-                     "us_per_step": round(sec / max(d, 1) * 1e6, 2)}
-        # the same fit as one captured graph (all steps recorded once, replayed)
-        g = rbd.FitGraph(bufs, X, tol=tol, rel=rel)
-        g.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
+        bufs, r = _with_driver(None, lambda: _time_fit(rbd, X, tol, rel, wl.d_max, reps, W))
+        # the same fit captured once as a graph and replayed
+        def graph():
+            g = rbd.FitGraph(bufs, X, tol=tol, rel=rel)
             g.replay()
-        torch.cuda.synchronize()
-        gsec = (time.perf_counter() - t0) / reps
-        g.close()
-        out[name]["graph_ms_per_fit"] = round(gsec * 1e3, 3)
-        out[name]["graph_greedy_steps_per_s"] = round(d / gsec, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.replay()
+            torch.cuda.synchronize()
+            gsec = (time.perf_counter() - t0) / reps
+            g.close()
+            return gsec
+        gsec = _with_driver(None, graph)
+        r["graph_ms_per_fit"] = round(gsec * 1e3, 4)
+        _, r1 = _with_driver("0", lambda: _time_fit(rbd, X, tol, rel, wl.d_max, reps, W))
+        r["one_launch_per_kernel"] = r1
+        out[name] = r
     return out
+
+
+def lowrank_section(rbd, K, W):
+    """The 512 x 256 low-rank workload (FP32 storage, abs tol 1e-8, d_max 64)."""
+    import torch
+
+    import synth
+    wl = synth.lowrank_spectrum(0)
+    X = torch.from_numpy(synth.quantize(wl.X, "f32")[0]).to("cuda:0")
+    reps = max(K, 1) * 10
+    _, r = _with_driver(None, lambda: _time_fit(rbd, X, wl.tol, False, wl.d_max, reps, W))
+    _, r1 = _with_driver("0", lambda: _time_fit(rbd, X, wl.tol, False, wl.d_max, reps, W))
+    r["one_launch_per_kernel"] = r1
+    r["workload"] = "low-rank spectrum 512x256 (sigma_i = 10^(-i/4), i < 32, + 1e-10 noise), FP32, tol 1e-8, d_max 64"
+    return r
+
+
+def stream_ceiling(rbd, t, reps=5):
+    """GB/s of one read of every byte of tensor t (non-temporal 16-byte loads, as the
+    X-scan reads X): the ceiling for a scan of that buffer."""
+    import torch
+    rbd.read_stream(t)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        rbd.read_stream(t)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = t.numel() * t.element_size()
+    return {"bytes": nbytes, "ms": round(ms, 4), "GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac": round(nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
 def batched_cpu_baseline(count=4096, sample=24, d_max=128, tol=1e-6):
@@ -535,6 +620,11 @@ def main():
         log("BF16 storage")
         runs["bf16"] = time_fits(rbd, X16, args.d_max, args.steps, args.warmup)
 
+    log("read-stream ceiling on X's own buffers")
+    ceiling = {"f32": stream_ceiling(rbd, X32)}
+    if "bf16" in runs:
+        ceiling["bf16"] = stream_ceiling(rbd, X16)
+
     phases = None
     if args.phases:
         phases = {k: phase_breakdown(rbd, X32 if k == "f32" else X16, args.d_max) for k in runs}
@@ -568,7 +658,8 @@ def main():
                      "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE, calibrated)",
                      "algorithmic_bytes": m * n * 4,
                      "kernel": "xscan (T(d,:) = xi' X)", "kernel_avg_ms": round(runs["f32"]["xscan_ms"], 4),
-                     "launches_timed": runs["f32"]["xscan_launches"]},
+                     "launches_timed": runs["f32"]["xscan_launches"],
+                     "read_stream_ceiling": ceiling["f32"]},
     }
     if "bf16" in runs:
         sec16, gbs16 = summary(runs["bf16"], 2)
@@ -576,7 +667,8 @@ def main():
                                "ms_per_step": round(sec16 * 1e3, 3),
                                "xscan_GBs": round(gbs16, 1), "xscan_frac": round(gbs16 / PEAK_HBM_GBS, 4),
                                "traffic": measured_traffic("bf16", m, n), "algorithmic_bytes": m * n * 2,
-                               "kernel_avg_ms": round(runs["bf16"]["xscan_ms"], 4)}
+                               "kernel_avg_ms": round(runs["bf16"]["xscan_ms"], 4),
+                               "read_stream_ceiling": ceiling["bf16"]}
     if args.weighted:
         w64 = torch.from_numpy(synth.disc_weights(args.grid)).to(dev)
         log("diagonal A-norm (disc weights), FP32 storage")
@@ -618,26 +710,29 @@ def main():
         torch.cuda.empty_cache()
     log("bump field 2048 x 2048 (FP32)")
     out["bump_field_2048"] = bump_field_section(rbd, args.steps, args.warmup)
+    log("low-rank 512 x 256 (FP32)")
+    out["lowrank_512x256"] = lowrank_section(rbd, args.steps, args.warmup)
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:
         out["equal_error"] = equal_error_report(runs, pf, args.sample_cols)
     for r in runs.values():
         del r["bufs"], r["res"]
-    if args.batched:
-        del X32
-        if "bf16" in runs:
-            del X16
-        torch.cuda.empty_cache()
+    nxt = not args.no_next_rows
+    del X32
+    if "bf16" in runs:
+        del X16
+    torch.cuda.empty_cache()
+    if nxt and not args.no_batched:
         out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup)
         if not args.no_cpu_baseline:
             out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
-    if args.classify:
-        torch.cuda.empty_cache()
-        out["classify"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
-    if args.backward:
+    if nxt and not args.no_backward:
         torch.cuda.empty_cache()
         out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    if nxt and not args.no_classify:
+        torch.cuda.empty_cache()
+        out["recognition"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(m, n=n)

@@ -57,7 +57,7 @@ struct FitPlan {
     // workgroups, rows per Gram-Schmidt workgroup, columns per workgroup
     bool loop = false;
     int lp_G = 0, lp_Gc = 0, lp_RB = 0, lp_CW = 0;
-    size_t o_lp_bv = 0, o_lp_bi = 0, o_lp_bc = 0, o_lp_part = 0;
+    size_t o_lp_bv = 0, o_lp_bi = 0, o_lp_bc = 0, o_lp_part = 0, o_lp_qc = 0, o_lp_ql = 0, o_lp_rp = 0;
     // workspace offsets (bytes)
     int ntiles = 0;
     size_t o_state, o_tickets, o_e2, o_base2, o_flist, o_bres_v, o_bres_i, o_v1, o_v2, o_h2, o_nu2, o_g, o_xp, o_M, o_mh, o_hw, o_ys,
@@ -73,8 +73,6 @@ struct FitPlan {
 // count assumes the MI355X's 256 CUs and is checked against the device at
 // launch.
 constexpr double kLoopMaxBytes = 64.0 * 1024 * 1024;
-constexpr int kLoopMaxG = 256;
-
 void plan_loop(FitPlan* P) {
     P->loop = false;
     const char* env = std::getenv("RBD_LOOP");
@@ -83,9 +81,13 @@ void plan_loop(FitPlan* P) {
     const double bytes = (double)P->m * (double)P->n * elem_bytes(P->xt);
     if (force != 1 && bytes > kLoopMaxBytes) return;
     if (P->m >= ((int64_t)1 << 30) || P->n >= ((int64_t)1 << 30)) return;
-    // one workgroup per 256 KB of X, a multiple of 8 (whole XCDs), 8 .. 256
-    int64_t G = (int64_t)(bytes / (256.0 * 1024));
-    G = std::max<int64_t>(8, std::min<int64_t>(kLoopMaxG, cdiv(std::max<int64_t>(G, 1), 8) * 8));
+    // one workgroup per 128 KB of X, a multiple of 8 (whole XCDs), 32 .. 256
+    // (measured on the 2048 x 2048 FP32 field: 32, 64, 128, 256 workgroups take
+    // 32.8, 28.2, 27.0, 29.5 us per fixed step; on the 512 x 256 one, 8, 16, 32,
+    // 64 workgroups take 31.1, 26.2, 23.5, 22.9 us per step: the exact refreshes
+    // are split over all of them)
+    int64_t G = (int64_t)(bytes / (128.0 * 1024));
+    G = std::max<int64_t>(32, std::min<int64_t>(kLoopMaxG, cdiv(std::max<int64_t>(G, 1), 8) * 8));
     // at most kLoopMaxCW columns and kLoopMaxRB Gram-Schmidt rows per workgroup;
     // up to 32 Gram-Schmidt workgroups of at least 64 rows
     const int64_t Gc = std::max<int64_t>(cdiv(P->m, kLoopMaxRB), std::min<int64_t>(32, cdiv(P->m, 64)));
@@ -196,6 +198,9 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
         P->o_lp_bi = take(8 * 2 * (size_t)P->lp_G);
         P->o_lp_bc = take(8 * 2 * (size_t)P->lp_G);
         P->o_lp_part = take(8 * (size_t)P->lp_Gc * (P->D + 1));
+        P->o_lp_qc = take(4 * (size_t)P->lp_G);
+        P->o_lp_ql = take(4 * (size_t)P->lp_G * P->lp_CW);
+        P->o_lp_rp = take(8 * (size_t)P->lp_G * n);
     }
     P->total = o;
     return true;
@@ -475,6 +480,9 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         lw.bval = reinterpret_cast<double*>(ws + P.o_lp_bv);
         lw.bidx = reinterpret_cast<int64_t*>(ws + P.o_lp_bi);
         lw.bcnt = reinterpret_cast<double*>(ws + P.o_lp_bc);
+        lw.qcnt = reinterpret_cast<int*>(ws + P.o_lp_qc);
+        lw.qlist = reinterpret_cast<int*>(ws + P.o_lp_ql);
+        lw.rpart = reinterpret_cast<double*>(ws + P.o_lp_rp);
         LoopOut lo{Y, T, pivots, col_err, err_hist, d_out, status, stop_reason};
         prof_begin(RBD_PHASE_LOOP, s);
         loop_kernel<Tx><<<P.lp_G, kLoopThreads, 0, s>>>(X, ldx, (int)P.m, (int)P.n, P.D, P.d_max, tol, rel, start, lo,
