@@ -37,9 +37,18 @@
 extern "C" {
 #endif
 
+/* In C++ the enumerations below have int as their fixed underlying type, so
+ * every int a C caller passes is a value of the type (and is then validated:
+ * an unknown value gives RBD_EINVAL). */
+#ifdef __cplusplus
+#define RBD_ENUM_BASE : int
+#else
+#define RBD_ENUM_BASE
+#endif
+
 /* Storage type of X (and V).  Arithmetic is always FP64: stored values are
  * widened exactly, products and sums are formed in FP64. */
-typedef enum {
+typedef enum RBD_ENUM_BASE {
     RBD_F32 = 0,
     RBD_BF16 = 1, /* bfloat16 bit patterns (uint16) */
     RBD_F16 = 2,  /* IEEE binary16 */
@@ -48,7 +57,7 @@ typedef enum {
 
 /* How `tol` is read: RBD_TOL_ABS uses tau = tol, RBD_TOL_REL uses
  * tau = tol * max_j ||x_j|| (the largest error before the first step). */
-typedef enum { RBD_TOL_ABS = 0, RBD_TOL_REL = 1 } rbd_tol_mode;
+typedef enum RBD_ENUM_BASE { RBD_TOL_ABS = 0, RBD_TOL_REL = 1 } rbd_tol_mode;
 
 /* Return / status codes. */
 enum {

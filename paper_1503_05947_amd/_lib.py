@@ -81,11 +81,15 @@ class LibraryMissing(ImportError):
     pass
 
 
-def load(path: str = LIB_PATH):
-    """Load librbd.so (built by ``_build.build_library``); raises if it is missing."""
+def load(path: str = None):
+    """Load librbd.so (built by ``_build.build_library``); raises if it is missing.
+    RBD_LIBRARY in the environment names another build of the same library (the
+    host-sanitized one of ``_build.build_host_sanitized``, for CPU tests)."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("RBD_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise LibraryMissing(f"{path} not found: build it with __graft_entry__.build() "
                              "(there is no fallback implementation)")

@@ -194,3 +194,27 @@ def test_noalloc_rejects_before_any_device_call(lib):
     assert call(100, 100, 10, ldx=99) == _lib.RBD_EINVAL
     assert call(0, 100, 10) == _lib.RBD_EINVAL
     assert lib.rbd_status_string(_lib.RBD_ETOOLARGE)
+
+
+@pytest.mark.parametrize("loop", ["0", "1"])
+def test_workspace_queries_over_many_shapes(lib, loop, monkeypatch):
+    """Every size query over shapes from tiny to the largest accepted, with the
+    persistent loop's plan on and off: the host's plan arithmetic (run under the
+    sanitizers by test_host_sanitized.py)."""
+    from paper_1503_05947_amd import _lib
+    monkeypatch.setenv("RBD_LOOP", loop)
+    out = ctypes.c_size_t(0)
+    shapes = [(1, 1, 1), (1, 7, 3), (9, 1, 4), (33, 17, 5), (512, 256, 64), (2048, 2048, 256), (1111, 777, 1024),
+              (70000, 40, 40), (262144, 1024, 256), (300, 250000, 24), (1 << 20, 4096, 512), (2000000, 8, 8),
+              (1 << 22, 64, 64)]
+    for m, n, dm in shapes:
+        for dt in (_lib.RBD_F32, _lib.RBD_BF16, _lib.RBD_F16, _lib.RBD_F64):
+            assert lib.rbd_fit_workspace_size(m, n, dm, dt, ctypes.byref(out)) == _lib.RBD_OK, (m, n, dm, dt)
+            assert out.value > 0
+            assert lib.rbd_fit_spd_workspace_size(m, n, dm, dt, ctypes.byref(out)) == _lib.RBD_OK
+            d = min(dm, m, n, _lib.RBD_MAX_D)
+            assert lib.rbd_project_workspace_size(m, d, n, dt, ctypes.byref(out)) == _lib.RBD_OK
+        d = min(dm, m, n, _lib.RBD_MAX_D)
+        assert lib.rbd_classify_workspace_size(m, d, n, ctypes.byref(out)) == _lib.RBD_OK
+        if d <= min(m, n):
+            assert lib.rbd_reconstruct_backward_workspace_size(m, n, d, ctypes.byref(out)) == _lib.RBD_OK
