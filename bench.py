@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="columns (parameter draws)")
     ap.add_argument("--d-max", type=int, default=512)
     ap.add_argument("--no-bf16", action="store_true")
+    ap.add_argument("--no-basis32", action="store_true", help="skip the BF16 fit with the basis kept in FP32")
     ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true", help="extra profiled fit with a per-phase breakdown")
@@ -53,6 +54,14 @@ def parse():
                     help="skip the batched fit: 4096 matrices, m, n log-uniform in [64, 1024], "
                          "spectrum 10^(-i/8), FP32, relative tol 1e-6")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batched-cache", default=None,
+                    help="load the batched matrices (stored values, packed) from this .npy file, or generate them "
+                         "and write it; with --write-batched-cache only write it and exit (so that a profiled run "
+                         "does no host generation)")
+    ap.add_argument("--write-batched-cache", action="store_true")
+    ap.add_argument("--next-rows-only", action="store_true",
+                    help="run only the batched, backward and recognition sections (for profiling them); the "
+                         "line then carries no headline value")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip the reconstruction backward: bump field 65536 x 2048 FP32, d = 128 pivots "
                          "fixed from a tol-0 fit, G ~ N(0,1)")
@@ -117,10 +126,10 @@ def ensure_built():
         _build.build_library()
 
 
-def time_fits(rbd, X, d_max, K, W, weights=None):
+def time_fits(rbd, X, d_max, K, W, weights=None, basis="f64"):
     import torch
     from paper_1503_05947_amd import _lib
-    bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device)
+    bufs = rbd.FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device, basis=basis)
     for _ in range(W):
         rbd.fit_into(bufs, X, tol=0.0, weights=weights)
     torch.cuda.synchronize()
@@ -171,7 +180,22 @@ def sampled_true_error(Y, T, X64J, J, ds):
     return out
 
 
-def equal_error_report(runs, pf, ncols):
+def indicator_gap(res, Xs, J):
+    """max over the sampled columns of |col_err_j - ||x_j - Y T_j|||, both of the
+    stored values, at the final d, in units of E_0 (pivot columns excluded)."""
+    import numpy as np
+    import torch
+    Jt = torch.from_numpy(J).to(Xs.device)
+    XJ = Xs.index_select(1, Jt).double()
+    R = XJ - res.Y @ res.T.index_select(1, Jt)
+    true = torch.linalg.vector_norm(R, dim=0).cpu().numpy()
+    ind = res.col_err.cpu().numpy()[J]
+    keep = ~np.isin(J, res.pivots.cpu().numpy())
+    E0 = float(res.err_hist[0])
+    return float(np.max(np.abs(true - ind)[keep]) / E0) if keep.any() else 0.0
+
+
+def equal_error_report(runs, pf, ncols, stored=None):
     import numpy as np
     import synth
     g = np.random.default_rng(12345)
@@ -198,14 +222,21 @@ def equal_error_report(runs, pf, ncols):
         del Y
         hist = res.err_hist.cpu().numpy()
         E0 = float(hist[0])                      # max ||x_j^P|| (stored values)
-        u = UNIT_ROUNDOFF[name]
+        storage, basis = run.get("storage", name), run.get("basis", "f64")
+        u = UNIT_ROUNDOFF[storage]
         # ||x64 - Y t|| <= ||x^P - Y t|| + ||x64 - x^P|| <= E_d + u/(1-u) * max ||x^P||
         q = u / (1.0 - u) * E0
         E0_64_bound = E0 / (1.0 + u)             # lower bound of max ||x64_j||
-        cert = [(float(hist[k]) + q) / E0_64_bound for k in range(d + 1)]
+        # an FP32 basis adds the downdate's indicator error, of order 2^-24 E_0^2 / E_d
+        # (taken with a factor 4; the sampled gap below is its measured value)
+        ind = (lambda k: 4.0 * 2.0 ** -24 * E0 * E0 / max(float(hist[k]), 1e-300)) if basis == "f32" else (lambda k: 0.0)
+        cert = [(float(hist[k]) + ind(k) + q) / E0_64_bound for k in range(d + 1)]
         steps = run["step_end_ms"]
-        entry = {"E0_stored": E0, "sampled_rel_err": [s / nx64.max() for s in sampled],
+        entry = {"storage": storage, "basis": basis, "E0_stored": E0,
+                 "sampled_rel_err": [s / nx64.max() for s in sampled],
                  "certified_rel_err_at_checkpoints": [cert[k] for k in ds], "time_to_eps_ms": {}}
+        if stored is not None and storage in stored:
+            entry["indicator_gap_final_d"] = indicator_gap(res, stored[storage], J)
         entry["time_to_eps_sampled_ms"] = {}
         # the certified bound cannot go below twice its storage term: at smaller eps
         # the storage type is not certifiable (null), whatever the fit reaches
@@ -231,6 +262,16 @@ def equal_error_report(runs, pf, ncols):
                                      if a32 and a16 and a32["ms"] and a16["ms"] else None)
             report[out] = ratio
         report["time_fp32_over_bf16"] = report["time_fp32_over_bf16_sampled"]
+    if "f32" in report["precisions"] and "bf16_basis_f32" in report["precisions"]:
+        for key, out in (("time_to_eps_ms", "time_fp32_over_bf16_basis_f32_certified"),
+                         ("time_to_eps_sampled_ms", "time_fp32_over_bf16_basis_f32_sampled")):
+            ratio = {}
+            for eps in EPS_BOTH:
+                a32 = report["precisions"]["f32"][key][f"{eps:g}"]
+                a16 = report["precisions"]["bf16_basis_f32"][key][f"{eps:g}"]
+                ratio[f"{eps:g}"] = (round(a32["ms"] / a16["ms"], 3)
+                                     if a32 and a16 and a32["ms"] and a16["ms"] else None)
+            report[out] = ratio
     report["note"] = ("certified: (E_d of the stored matrix + storage unit roundoff * max ||x||) / max ||x64||, "
                       "an upper bound on max_j ||x64_j - Y T_j|| / max_j ||x64_j|| at every d, null below twice its storage "
                       "term; sampled: the same quantity evaluated exactly on the sampled columns at the checkpoints "
@@ -249,11 +290,23 @@ def _gen_batched(args):
     return synth.quantize(synth.batched_matrix(seed, b, m, n), "f32")[0]
 
 
-def batched_section(rbd, count, K, W, d_max=128, tol=1e-6):
-    import multiprocessing as mp
-
+def batched_inputs(count, cache=None):
+    """The stored values of the batch, packed (X_b row-major, back to back), from
+    `cache` when it exists, else generated in a pool of fresh interpreters (and
+    written to `cache` when given)."""
     import numpy as np
-    import torch
+    if cache and os.path.exists(cache):
+        log(f"batched: loading {cache}")
+        return np.load(cache, allow_pickle=False)
+    mats = generate_batched(count)
+    Xp = np.concatenate([A.reshape(-1) for A in mats])
+    if cache:
+        np.save(cache, Xp, allow_pickle=False)
+    return Xp
+
+
+def generate_batched(count):
+    import multiprocessing as mp
 
     import synth
     ms, ns = synth.batched_sizes(0, count=count)
@@ -279,10 +332,18 @@ def batched_section(rbd, count, K, W, d_max=128, tol=1e-6):
             else:
                 os.environ[k] = v
     log(f"batched: generated in {time.perf_counter() - t0:.1f} s")
+    return mats
+
+
+def batched_section(rbd, count, K, W, d_max=128, tol=1e-6, cache=None):
+    import numpy as np
+    import torch
+
+    import synth
+    ms, ns = synth.batched_sizes(0, count=count)
     dev = torch.device("cuda:0")
     plan = rbd.BatchPlan(ms, ns, d_max, torch.float32, dev)
-    Xp = torch.from_numpy(np.concatenate([A.reshape(-1) for A in mats])).to(dev)
-    del mats
+    Xp = torch.from_numpy(batched_inputs(count, cache)).to(dev)
     cfg = plan.autotune(Xp, tol=tol, rel=True)
     for _ in range(W):
         plan.run(Xp, tol=tol, rel=True)
@@ -582,12 +643,34 @@ def cpu_baseline(full_m, grid_sample=256, n=4096, steps=24):
                        f"and a 1-step fit: {per_step:.3f} s/step), scaled by m_full/m_sample = {scale:g}")}
 
 
+def next_rows(rbd, args):
+    import torch
+    out = {}
+    if not args.no_batched:
+        out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup, cache=args.batched_cache)
+        if not args.no_cpu_baseline:
+            out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
+    if not args.no_backward:
+        torch.cuda.empty_cache()
+        out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    if not args.no_classify:
+        torch.cuda.empty_cache()
+        out["recognition"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path. "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.write_batched_cache:
+        if not args.batched_cache:
+            sys.exit("--write-batched-cache needs --batched-cache PATH")
+        batched_inputs(args.batch_count, args.batched_cache)
+        log(f"wrote {args.batched_cache}")
+        return
     ensure_built()
     import numpy as np
     import torch
@@ -597,6 +680,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.next_rows_only:
+        print(json.dumps({"next_rows_only": True, **next_rows(rbd, args)}), flush=True)
+        return
     pf = synth.parametric_field(seed=0, grid=args.grid, n=args.n)
     m, n = pf.m, pf.n
     log(f"generating the parametric field {m} x {n} (FP32) on {torch.cuda.get_device_name(0)}")
@@ -619,6 +705,10 @@ def main():
         X16 = X32.to(torch.bfloat16)
         log("BF16 storage")
         runs["bf16"] = time_fits(rbd, X16, args.d_max, args.steps, args.warmup)
+        if not args.no_basis32:
+            log("BF16 storage, basis kept in FP32")
+            runs["bf16_basis_f32"] = time_fits(rbd, X16, args.d_max, args.steps, args.warmup, basis="f32")
+            runs["bf16_basis_f32"].update(storage="bf16", basis="f32")
 
     log("read-stream ceiling on X's own buffers")
     ceiling = {"f32": stream_ceiling(rbd, X32)}
@@ -627,7 +717,7 @@ def main():
 
     phases = None
     if args.phases:
-        phases = {k: phase_breakdown(rbd, X32 if k == "f32" else X16, args.d_max) for k in runs}
+        phases = {k: phase_breakdown(rbd, X32 if k == "f32" else X16, args.d_max) for k in runs if k != "bf16_basis_f32"}
 
     def summary(r, sx):
         sec = r["seconds"] / r["fits"]
@@ -664,11 +754,20 @@ def main():
     if "bf16" in runs:
         sec16, gbs16 = summary(runs["bf16"], 2)
         out["bf16_storage"] = {"value": round(runs["bf16"]["d"] / sec16, 3), "unit": "greedy steps/s",
-                               "ms_per_step": round(sec16 * 1e3, 3),
+                               "ms_per_fit": round(sec16 * 1e3, 3),
                                "xscan_GBs": round(gbs16, 1), "xscan_frac": round(gbs16 / PEAK_HBM_GBS, 4),
                                "traffic": measured_traffic("bf16", m, n), "algorithmic_bytes": m * n * 2,
                                "kernel_avg_ms": round(runs["bf16"]["xscan_ms"], 4),
                                "read_stream_ceiling": ceiling["bf16"]}
+    if "bf16_basis_f32" in runs:
+        r = runs["bf16_basis_f32"]
+        secb, gbsb = summary(r, 2)
+        out["bf16_storage_basis_f32"] = {
+            "value": round(r["d"] / secb, 3), "unit": "greedy steps/s", "ms_per_fit": round(secb * 1e3, 3),
+            "xscan_GBs": round(gbsb, 1), "xscan_frac": round(gbsb / PEAK_HBM_GBS, 4),
+            "kernel_avg_ms": round(r["xscan_ms"], 4), "speedup_vs_fp64_basis": round(sec16 / secb, 3),
+            "note": "rbd_fit_basis(RBD_BASIS_F32): the basis is stored in FP32 while the loop runs, all "
+                    "arithmetic FP64; accuracy in equal_error.precisions.bf16_basis_f32"}
     if args.weighted:
         w64 = torch.from_numpy(synth.disc_weights(args.grid)).to(dev)
         log("diagonal A-norm (disc weights), FP32 storage")
@@ -715,7 +814,10 @@ def main():
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:
-        out["equal_error"] = equal_error_report(runs, pf, args.sample_cols)
+        stored = {"f32": X32}
+        if "bf16" in runs:
+            stored["bf16"] = X16
+        out["equal_error"] = equal_error_report(runs, pf, args.sample_cols, stored)
     for r in runs.values():
         del r["bufs"], r["res"]
     nxt = not args.no_next_rows
@@ -723,16 +825,8 @@ def main():
     if "bf16" in runs:
         del X16
     torch.cuda.empty_cache()
-    if nxt and not args.no_batched:
-        out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup)
-        if not args.no_cpu_baseline:
-            out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
-    if nxt and not args.no_backward:
-        torch.cuda.empty_cache()
-        out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
-    if nxt and not args.no_classify:
-        torch.cuda.empty_cache()
-        out["recognition"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+    if nxt:
+        out.update(next_rows(rbd, args))
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(m, n=n)

@@ -55,6 +55,12 @@ typedef enum RBD_ENUM_BASE {
     RBD_F64 = 3
 } rbd_dtype;
 
+/* Storage of the basis while a fit runs (rbd_fit_basis).  RBD_BASIS_F64 is
+ * rbd_fit's.  RBD_BASIS_F32 keeps Y in FP32 in the workspace (half the bytes
+ * of the pass over Y each step), with all arithmetic still FP64, and writes
+ * its FP64 copy to the output Y at the end. */
+typedef enum RBD_ENUM_BASE { RBD_BASIS_F64 = 0, RBD_BASIS_F32 = 1 } rbd_basis;
+
 /* How `tol` is read: RBD_TOL_ABS uses tau = tol, RBD_TOL_REL uses
  * tau = tol * max_j ||x_j|| (the largest error before the first step). */
 typedef enum RBD_ENUM_BASE { RBD_TOL_ABS = 0, RBD_TOL_REL = 1 } rbd_tol_mode;
@@ -124,6 +130,33 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
             double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
             int32_t* d_out, int32_t* status, int32_t* stop_reason,
             void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * rbd_fit_basis -- rbd_fit with a choice of how the basis is stored while
+ * the loop runs (rbd_fit_basis(..., RBD_BASIS_F64, ...) is rbd_fit).  With
+ * RBD_BASIS_F32 every basis vector xi_k is formed in FP64 as by rbd_fit and
+ * stored rounded to FP32; the Gram-Schmidt passes and the exact refreshes
+ * read the stored (rounded) vectors, while the row T(k, :) is formed from
+ * the FP64 vector before rounding.  The output Y holds the stored values
+ * (orthonormal to about 1e-7 instead of 1e-15).  The
+ * downdated errors then carry, between exact refreshes, an absolute error of
+ * order 2^-24 ||x_j||^2 / e_j in e_j (the rounded basis is orthonormal only
+ * to FP32 precision), so the mode is meant for data whose errors stay well
+ * above 2^-12 ||x_j||: BF16 storage (unit roundoff 2^-9), whose fits it
+ * speeds up by halving the bytes of the pass over Y.  The exact refreshes and
+ * their trigger are those of rbd_fit.  The persistent single-launch loop is
+ * not used in this mode.
+ *   basis       RBD_BASIS_F64 or RBD_BASIS_F32; other arguments as for rbd_fit.
+ *   workspace   at least rbd_fit_basis_workspace_size() bytes.
+ * Returns what rbd_fit returns; RBD_EINVAL for an unknown `basis`.
+ */
+int rbd_fit_basis_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, rbd_basis basis,
+                                 size_t* bytes);
+int rbd_fit_basis(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
+                  double tol, rbd_tol_mode mode, int32_t d_max, int64_t start, rbd_basis basis,
+                  double* Y, double* T, int64_t* pivots, double* col_err, double* err_hist,
+                  int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                  void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * rbd_fit_noalloc -- rbd_fit for callers that cannot allocate device memory

@@ -32,6 +32,14 @@ def _torch():
     return torch
 
 
+def basis_code(basis) -> int:
+    """'f64' (rbd_fit) or 'f32' (the basis stored in FP32 while the loop runs, rbd_fit_basis)."""
+    codes = {"f64": _lib.RBD_BASIS_F64, "f32": _lib.RBD_BASIS_F32}
+    if basis not in codes:
+        raise ValueError(f"basis must be 'f64' or 'f32', not {basis!r}")
+    return codes[basis]
+
+
 def dtype_code(dtype) -> int:
     torch = _torch()
     table = {torch.float32: _lib.RBD_F32, torch.bfloat16: _lib.RBD_BF16,
@@ -92,13 +100,21 @@ class FitBuffers:
     """Outputs and workspace of one rbd_fit configuration, reusable across calls
     (``spd``: sized for rbd_fit_spd as well)."""
 
-    def __init__(self, m: int, n: int, d_max: int, dtype, device, spd: bool = False, workspace: bool = True):
+    def __init__(self, m: int, n: int, d_max: int, dtype, device, spd: bool = False, workspace: bool = True,
+                 basis: str = "f64"):
         torch = _torch()
         self.m, self.n, self.d_max, self.dtype = int(m), int(n), int(d_max), dtype
         code = dtype_code(dtype)
         self.spd = bool(spd)
-        self.ws_bytes = (_lib.fit_spd_workspace_size if spd else _lib.fit_workspace_size)(
-            self.m, self.n, self.d_max, code) if workspace else 0
+        self.basis = basis_code(basis)
+        if spd and self.basis != _lib.RBD_BASIS_F64:
+            raise ValueError("the FP32 basis is for A = I fits only")
+        if not workspace:
+            self.ws_bytes = 0
+        elif spd:
+            self.ws_bytes = _lib.fit_spd_workspace_size(self.m, self.n, self.d_max, code)
+        else:
+            self.ws_bytes = _lib.fit_workspace_size(self.m, self.n, self.d_max, code, self.basis)
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
         self.Y = torch.empty((self.m, self.d_max), **f64)
@@ -153,9 +169,11 @@ def fit_into(bufs: FitBuffers, X, tol: float = 0.0, rel: bool = False, start: in
                                  A.indices.data_ptr(), A.values.data_ptr(), A.nnz, float(tol), mode, bufs.d_max,
                                  int(start), *outs)
         elif weights is None:
-            rc = lib.rbd_fit(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol), mode,
-                             bufs.d_max, int(start), *outs)
+            rc = lib.rbd_fit_basis(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0), float(tol), mode,
+                                   bufs.d_max, int(start), bufs.basis, *outs)
         else:
+            if bufs.basis != _lib.RBD_BASIS_F64:
+                raise ValueError("the FP32 basis is for A = I fits only")
             rc = lib.rbd_fit_weighted(X.data_ptr(), dtype_code(X.dtype), bufs.m, bufs.n, X.stride(0),
                                       weights.data_ptr(), float(tol), mode, bufs.d_max, int(start), *outs)
     _lib.check(rc, "rbd_fit")
@@ -193,6 +211,8 @@ class FitGraph:
         _check_matrix(X, "X")
         if tuple(X.shape) != (bufs.m, bufs.n) or X.dtype != bufs.dtype:
             raise ValueError("X does not match the buffers' shape/dtype")
+        if bufs.basis != _lib.RBD_BASIS_F64:
+            raise ValueError("the captured fit keeps the basis in FP64")
         if weights is not None and (weights.dtype != torch.float64 or weights.dim() != 1
                                     or weights.numel() != bufs.m or weights.device != X.device
                                     or not weights.is_contiguous()):
@@ -238,17 +258,18 @@ class FitGraph:
 
 
 def fit(X, tol: float = 0.0, d_max: int = 64, rel: bool = False, start: int = -1, stream=None,
-        weights=None, A: "CsrMatrix | None" = None) -> FitResult:
+        weights=None, A: "CsrMatrix | None" = None, basis: str = "f64") -> FitResult:
     """Algorithm 1 on a device matrix X (m x n, f32/bf16/f16/f64 storage).
 
     ``tol`` is eps_R (absolute, or relative to max_j ||x_j|| when ``rel``);
     ``start < 0`` starts from the column of largest norm; ``weights`` (float64,
     m values > 0) selects the diagonal A-norm of section 3.2, ``A`` (CsrMatrix)
-    a general SPD A-norm.  Waits for the
+    a general SPD A-norm; ``basis='f32'`` keeps the basis in FP32 while the
+    loop runs (rbd_fit_basis, for BF16-stored data).  Waits for the
     device and returns views of the first d basis vectors / rows of T.
     """
     torch = _torch()
-    bufs = FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device, spd=A is not None)
+    bufs = FitBuffers(X.shape[0], X.shape[1], d_max, X.dtype, X.device, spd=A is not None, basis=basis)
     fit_into(bufs, X, tol=tol, rel=rel, start=start, stream=stream, weights=weights, A=A)
     (stream or torch.cuda.current_stream(X.device)).synchronize()
     return bufs.result()

@@ -11,6 +11,8 @@ LIB_PATH = os.path.join(HERE, "librbd.so")
 RBD_F32, RBD_BF16, RBD_F16, RBD_F64 = 0, 1, 2, 3
 # rbd_tol_mode
 RBD_TOL_ABS, RBD_TOL_REL = 0, 1
+# rbd_basis
+RBD_BASIS_F64, RBD_BASIS_F32 = 0, 1
 # status codes
 RBD_OK, RBD_EINVAL, RBD_ENONFINITE, RBD_EWORKSPACE, RBD_EDEVICE, RBD_EMATRIX, RBD_ETOOLARGE = 0, -1, -2, -3, -4, -5, -6
 RBD_NOALLOC_MAX_BYTES = 64 << 20
@@ -25,6 +27,10 @@ SIGNATURES = {
     "rbd_fit_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.POINTER(_sz)]),
     "rbd_fit": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64,
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "rbd_fit_basis_workspace_size": (ctypes.c_int, [_i64, _i64, _i32, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.POINTER(_sz)]),
+    "rbd_fit_basis": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64, ctypes.c_int,
+                                     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "rbd_fit_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_int, _i32, _i64,
                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "rbd_fit_weighted": (ctypes.c_int, [_vp, ctypes.c_int, _i64, _i64, _i64, _vp, _dp, ctypes.c_int, _i32, _i64,
@@ -117,9 +123,10 @@ def check(code: int, what: str) -> None:
         raise RuntimeError(f"{what}: {status_string(code)} (code {code})")
 
 
-def fit_workspace_size(m: int, n: int, d_max: int, dtype: int) -> int:
+def fit_workspace_size(m: int, n: int, d_max: int, dtype: int, basis: int = RBD_BASIS_F64) -> int:
     out = ctypes.c_size_t(0)
-    check(load().rbd_fit_workspace_size(m, n, d_max, dtype, ctypes.byref(out)), "rbd_fit_workspace_size")
+    check(load().rbd_fit_basis_workspace_size(m, n, d_max, dtype, basis, ctypes.byref(out)),
+          "rbd_fit_basis_workspace_size")
     return out.value
 
 

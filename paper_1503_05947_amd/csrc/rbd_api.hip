@@ -14,6 +14,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rbd.h"
@@ -56,6 +57,8 @@ struct FitPlan {
     // persistent loop (A = I, cache-resident X): workgroups, Gram-Schmidt
     // workgroups, rows per Gram-Schmidt workgroup, columns per workgroup
     bool loop = false;
+    bool y32 = false;           // the basis is kept in FP32 (o_yf) and copied out at the end
+    size_t o_yf = 0;
     int lp_G = 0, lp_Gc = 0, lp_RB = 0, lp_CW = 0;
     size_t o_lp_bv = 0, o_lp_bi = 0, o_lp_bc = 0, o_lp_part = 0, o_lp_qc = 0, o_lp_ql = 0, o_lp_rp = 0;
     // workspace offsets (bytes)
@@ -109,8 +112,10 @@ void plan_loop(FitPlan* P) {
     P->lp_CW = CW;
 }
 
-bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P) {
+bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P, int basis = RBD_BASIS_F64) {
     if (m < 1 || n < 1 || d_max < 1) return false;
+    if (basis != RBD_BASIS_F64 && basis != RBD_BASIS_F32) return false;
+    P->y32 = (basis == RBD_BASIS_F32);
     if (elem_bytes(xt) == 0) return false;
     if (n >= (int64_t)INT32_MAX || m >= ((int64_t)1 << 40)) return false;
     P->m = m;
@@ -157,7 +162,8 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->rf_grid = (int)cdiv(n, 256);
 
     P->ntickets = (int)std::max<int64_t>(P->up_ncb + 1, P->cg_ngroups + 1) + 8;
-    plan_loop(P);
+    if (!P->y32) plan_loop(P);
+    else P->loop = false;
 
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -193,6 +199,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
         std::max<size_t>(((size_t)P->up_SG + kp_max + 1) * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
     P->o_l2 = take(8 * l2_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * n);
+    if (P->y32) P->o_yf = take(4 * (size_t)m * d_max);
     if (P->loop) {
         P->o_lp_bv = take(8 * 2 * (size_t)P->lp_G);
         P->o_lp_bi = take(8 * 2 * (size_t)P->lp_G);
@@ -359,15 +366,15 @@ void launch_gvec2(const FitPlan& P, double* Y, const State* st, int d, const dou
                                                                             hw, w, ys, v2, g);
 }
 
-template <int KC>
-void launch_cgs1_lag(const FitPlan& P, const double* xp, double* Y, const double* T, State* st, int d,
-                     const double* v1p, const double* h2p, double* v1, double* ys, double* part, hipStream_t s) {
+template <int KC, typename Tb>
+void launch_cgs1_lag(const FitPlan& P, const double* xp, Tb* Y, const double* T, State* st, int d,
+                     const double* v1p, const double* h2p, double* v1, Tb* ys, double* part, hipStream_t s) {
     if (y_stream(P, d))
-        cgs1_lag_kernel<KC, rows_in_flight(KC), true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+        cgs1_lag_kernel<KC, rows_in_flight(KC), true, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
                                                                               P.cg_rows, v1p, h2p, v1, ys, part,
                                                                               std::max(P.D, 1));
     else
-        cgs1_lag_kernel<KC, rows_in_flight(KC), false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+        cgs1_lag_kernel<KC, rows_in_flight(KC), false, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
                                                                                P.cg_rows, v1p, h2p, v1, ys, part,
                                                                                std::max(P.D, 1));
 }
@@ -378,27 +385,27 @@ void launch_gather(const FitPlan& P, const Tx* X, int64_t ldx, const State* st, 
     gather_col_kernel<Tx><<<g, 256, 0, s>>>(X, ldx, P.m, st, xp);
 }
 
-template <int KC, bool FINAL>
-void launch_ycol(const FitPlan& P, double* Y, const State* st, int d, const double* v1a, const double* v1b,
-                 const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
+template <int KC, bool FINAL, typename Tb>
+void launch_ycol(const FitPlan& P, Tb* Y, const State* st, int d, const double* v1a, const double* v1b,
+                 const double* h2a, const double* h2b, const Tb* ys, hipStream_t s) {
     // FINAL: the column index is only known on the device; size the choice by D
     if (y_stream(P, FINAL ? P.D : d))
-        ycol_kernel<KC, rows_in_flight(KC), FINAL, true><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
+        ycol_kernel<KC, rows_in_flight(KC), FINAL, true, Tb><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
                                                                                  v1a, v1b, h2a, h2b, ys);
     else
-        ycol_kernel<KC, rows_in_flight(KC), FINAL, false><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
+        ycol_kernel<KC, rows_in_flight(KC), FINAL, false, Tb><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
                                                                                   v1a, v1b, h2a, h2b, ys);
 }
 
-template <bool FINAL>
-void launch_ycol_kc(int kc, const FitPlan& P, double* Y, const State* st, int d, const double* v1a,
-                    const double* v1b, const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
+template <bool FINAL, typename Tb>
+void launch_ycol_kc(int kc, const FitPlan& P, Tb* Y, const State* st, int d, const double* v1a,
+                    const double* v1b, const double* h2a, const double* h2b, const Tb* ys, hipStream_t s) {
     switch (kc) {
-        case 1: launch_ycol<1, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
-        case 2: launch_ycol<2, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
-        case 4: launch_ycol<4, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
-        case 8: launch_ycol<8, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
-        default: launch_ycol<16, FINAL>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 1: launch_ycol<1, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 2: launch_ycol<2, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 4: launch_ycol<4, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        case 8: launch_ycol<8, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
+        default: launch_ycol<16, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
     }
 }
 
@@ -513,18 +520,23 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     // alternate between two buffers by the parity of the step.
     double* const v1s[2] = {v1, v2};
     double* const h2s[2] = {h2, h2 + RBD_MAX_D + 1};
-    for (int d = 0; !W && d < P.D; ++d) {
+    // the basis is kept in Y itself, or in FP32 in the workspace (copied out by the epilogue)
+    float* const Yf = P.y32 ? reinterpret_cast<float*>(ws + P.o_yf) : nullptr;
+    auto identity_steps = [&](auto* Yb) -> int {
+    using Tb = std::remove_pointer_t<decltype(Yb)>;
+    Tb* const ysb = reinterpret_cast<Tb*>(ys);          // staged slots in the basis' storage type
+    for (int d = 0; d < P.D; ++d) {
         const int c = d & 1;
         const int kc = kc_for(d);
         prof_begin(RBD_PHASE_CGS1, s);
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs1_lag<1>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 2: launch_cgs1_lag<2>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 4: launch_cgs1_lag<4>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 8: launch_cgs1_lag<8>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            default: launch_cgs1_lag<16>(P, xp, Y, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
+            case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
+            case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
+            case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
+            default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
@@ -552,9 +564,9 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
         // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
-        launch_ycol_kc<false>(kc, P, Y, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
+        launch_ycol_kc<false>(kc, P, Yb, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ysb, s);
         RBD_LAUNCH_CHECK();
-        resid_mfma_kernel<Tx><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+        resid_mfma_kernel<Tx, false, Tb><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Yb, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, nullptr);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID, s);
@@ -564,6 +576,12 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID_FINISH, s);
         prof_step(s);
+    }
+    return RBD_OK;
+    };
+    if (!W) {
+        const int rc = Yf ? identity_steps(Yf) : identity_steps(Y);
+        if (rc != RBD_OK) return rc;
     }
     // diagonal A: two passes over Y per step (M = Y'WY kept up to date)
     double* const avec = h2 + RBD_MAX_D + 1;     // a = Y'(w . v1) and sum w v1^2
@@ -636,12 +654,14 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         RBD_LAUNCH_CHECK();
     } else {
         // the last basis vector is still implicit: write it
-        launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], ys,
-                             s);
+        if (Yf)
+            launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Yf, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], reinterpret_cast<const float*>(ys), s);
+        else
+            launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
         RBD_LAUNCH_CHECK();
     }
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
-                                       stop_reason);
+                                       stop_reason, Yf);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_EPILOGUE, s);
     return RBD_OK;
@@ -946,8 +966,8 @@ int rbd_fit_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, si
 static int check_fit_args(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol,
                           rbd_tol_mode mode, int32_t d_max, int64_t start, const double* Y, const double* T,
                           const int64_t* pivots, const double* col_err, const double* err_hist, const int32_t* d_out,
-                          const int32_t* status, FitPlan* P) {
-    if (!make_fit_plan(m, n, d_max, xt, P)) return RBD_EINVAL;
+                          const int32_t* status, FitPlan* P, int basis = RBD_BASIS_F64) {
+    if (!make_fit_plan(m, n, d_max, xt, P, basis)) return RBD_EINVAL;
     if (!X || !Y || !T || !pivots || !col_err || !err_hist || !d_out || !status) return RBD_EINVAL;
     if (ldx < n) return RBD_EINVAL;
     if (!(tol >= 0.0) || tol == HUGE_VAL) return RBD_EINVAL;
@@ -959,11 +979,12 @@ static int check_fit_args(const void* X, rbd_dtype xt, int64_t m, int64_t n, int
 static int fit_entry(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
                      int32_t d_max, int64_t start, double* Y, double* T, int64_t* pivots, double* col_err,
                      double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason, void* workspace,
-                     size_t workspace_bytes, void* stream, const double* w) {
+                     size_t workspace_bytes, void* stream, const double* w, int basis = RBD_BASIS_F64) {
     FitPlan P;
     const int rc = check_fit_args(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist,
-                                  d_out, status, &P);
+                                  d_out, status, &P, basis);
     if (rc != RBD_OK) return rc;
+    if (w && P.y32) return RBD_EINVAL;          // the FP32 basis is for A = I only
     if (!workspace) return RBD_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return RBD_EINVAL;
     if (workspace_bytes < P.total) return RBD_EWORKSPACE;
@@ -993,6 +1014,23 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, doub
             void* stream) {
     return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
                      stop_reason, workspace, workspace_bytes, stream, nullptr);
+}
+
+int rbd_fit_basis_workspace_size(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, rbd_basis basis,
+                                 size_t* bytes) {
+    if (!bytes) return RBD_EINVAL;
+    FitPlan P;
+    if (!make_fit_plan(m, n, d_max, xt, &P, (int)basis)) return RBD_EINVAL;
+    *bytes = P.total;
+    return RBD_OK;
+}
+
+int rbd_fit_basis(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol, rbd_tol_mode mode,
+                  int32_t d_max, int64_t start, rbd_basis basis, double* Y, double* T, int64_t* pivots,
+                  double* col_err, double* err_hist, int32_t* d_out, int32_t* status, int32_t* stop_reason,
+                  void* workspace, size_t workspace_bytes, void* stream) {
+    return fit_entry(X, xt, m, n, ldx, tol, mode, d_max, start, Y, T, pivots, col_err, err_hist, d_out, status,
+                     stop_reason, workspace, workspace_bytes, stream, nullptr, (int)basis);
 }
 
 int rbd_fit_noalloc(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx, double tol,

@@ -17,8 +17,8 @@ namespace rbd {
 // One element of Y in a pass over its rows.  NT: a non-temporal load, for
 // passes whose Y is larger than the caches (Y is read once per greedy step,
 // so nothing it would keep in the caches is used again).
-template <bool NT>
-__device__ __forceinline__ double ld_y(const double* p) {
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_y(const T* p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }

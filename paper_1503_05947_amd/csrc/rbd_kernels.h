@@ -214,37 +214,6 @@ __global__ __launch_bounds__(256) void xscan_kernel(const Tx* __restrict__ X, in
 }
 
 // ---------------------------------------------------------------------------
-// read_stream: every 16-byte vector of a buffer read once (the X-scan's loads,
-// non-temporal when NT), values folded into a register and discarded.  The
-// bandwidth a scan of that buffer can reach.  Workgroups own contiguous
-// chunks; eight loads in flight per thread.
-// ---------------------------------------------------------------------------
-template <bool NT>
-__global__ __launch_bounds__(256) void read_stream_kernel(const u32x4* __restrict__ v, int64_t nvec,
-                                                          unsigned key, unsigned* __restrict__ sink) {
-    const int64_t per = (nvec + gridDim.x - 1) / gridDim.x;
-    const int64_t a = (int64_t)blockIdx.x * per, b = min(nvec, a + per);
-    unsigned acc = 0u;
-    constexpr int U = 8;
-    int64_t i = a + threadIdx.x;
-    for (; i + (U - 1) * (int64_t)blockDim.x < b; i += U * (int64_t)blockDim.x) {
-        u32x4 r[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const u32x4* q = v + i + u * (int64_t)blockDim.x;
-            r[u] = NT ? __builtin_nontemporal_load(q) : *q;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc ^= r[u].x ^ r[u].y ^ r[u].z ^ r[u].w;
-    }
-    for (; i < b; i += blockDim.x) {
-        const u32x4 r = v[i];
-        acc ^= r.x ^ r.y ^ r.z ^ r.w;
-    }
-    if (acc == key) *sink = acc;     // keeps the loads; practically never taken
-}
-
-// ---------------------------------------------------------------------------
 // update: finish the column sums (slab groups, fixed order), then either
 // initialise the errors (INIT) or downdate them (STEP), and take the
 // lowest-index argmax.  One block per 256 columns; the last block to arrive
@@ -393,9 +362,48 @@ __device__ __forceinline__ double lane_bcast(double v, int u) {
 // below 8 floor(c / 8) are in Y and columns [8 floor(c / 8), c) only in ys;
 // ys_flush / ycol copy the staged ones into Y wherever Y must be complete
 // (before an exact refresh, after the loop).
-__device__ __forceinline__ const double* y_src(const double* Y, int64_t ldy, const double* ys, int64_t m, int64_t r,
-                                               int k, int yb) {
+template <typename Tb>
+__device__ __forceinline__ const Tb* y_src(const Tb* Y, int64_t ldy, const Tb* ys, int64_t m, int64_t r, int k,
+                                           int yb) {
     return k < yb ? Y + r * ldy + k : ys + (int64_t)min(k - yb, 7) * m + r;
+}
+
+// Entries (rb + u, lane + 64 c) of the basis for u < RU, c < KC, zero for rows
+// >= r1 or columns >= cols.  FP64: loads under the bounds test (the compiler
+// issues them all before the first use).  FP32: every load is issued from a
+// clamped address (row min(r, r1 - 1); a column past the end reads staged
+// slot 7 of that row) and the bounds test selects after the widening, since
+// a widening inside the test would make each load wait for its data.
+template <bool NT, int RU, int KC, typename Tb>
+__device__ __forceinline__ void load_y_rows(double (&y)[RU][KC], const Tb* Y, int64_t ldy, const Tb* ys, int64_t m,
+                                            int64_t rb, int64_t r1, int lane, int cols, int yb) {
+    if constexpr (sizeof(Tb) == 8) {
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = rb + u;
+            const bool ok = r < r1;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const int k = lane + kWave * c;
+                y[u][c] = (ok && k < cols) ? (double)ld_y<NT>(y_src<Tb>(Y, ldy, ys, m, r, k, yb)) : 0.0;
+            }
+        }
+    } else {
+        Tb raw[RU][KC];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t r = min(rb + u, r1 - 1);
+#pragma unroll
+            for (int c = 0; c < KC; ++c) raw[u][c] = ld_y<NT>(y_src<Tb>(Y, ldy, ys, m, r, lane + kWave * c, yb));
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const double v = (double)raw[u][c];
+                y[u][c] = (rb + u < r1 && lane + kWave * c < cols) ? v : 0.0;
+            }
+    }
 }
 
 // ys_flush: copies the staged columns [8 floor(c / 8), c) into Y, with c the
@@ -850,14 +858,14 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 // stages it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
 // share of h2 = Y(:, 0:d)' v1 (part[blk*ldp + k], k < d) and of ||v1||^2
 // (part[blk*ldp + d]).
-template <int KC, int RU, bool NT>
+template <int KC, int RU, bool NT, typename Tb = double>
 __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict__ xp, int64_t m,
-                                                        double* __restrict__ Y, int64_t ldy,
+                                                        Tb* __restrict__ Y, int64_t ldy,
                                                         const double* __restrict__ T, int64_t ldt,
                                                         State* __restrict__ st, int d, int rows_per_blk,
                                                         const double* __restrict__ v1p,
                                                         const double* __restrict__ h2p, double* __restrict__ v1,
-                                                        double* __restrict__ ys, double* __restrict__ part,
+                                                        Tb* __restrict__ ys, double* __restrict__ part,
                                                         int64_t ldp) {
     static_assert(RU <= kWave / 8, "eight lanes per row in flight for the block write");
     if (st->stop) return;
@@ -894,19 +902,10 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         const double xl = okl ? xp[rl] : 0.0;
         const double vl = (okl && dl >= 0) ? v1p[rl] : 0.0;
         const bool okb = blk && ju < RU && rb + ju < r1;
-        const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
+        const Tb sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : Tb(0);
         double y[RU][KC];
         double dots[2 * RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = rb + u;
-            const bool ok = r < r1;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                const int k = lane + kWave * c;
-                y[u][c] = (ok && k < dl) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
-            }
-        }
+        load_y_rows<NT, RU, KC>(y, Y, ldy, ys, m, rb, r1, lane, dl, yb);
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             double a = 0.0, b = 0.0;
@@ -922,7 +921,8 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         double vo = 0.0, yo = 0.0, yb7 = 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            const double yl = dl >= 0 ? (lane_bcast(vl, u) - dots[u]) * invp : 0.0;   // rows past the end: 0
+            // rows past the end: 0; the stored (Tb) value is what every pass uses
+            const double yl = dl >= 0 ? (double)(Tb)((lane_bcast(vl, u) - dots[u]) * invp) : 0.0;
             const double v = lane_bcast(xl, u) - dots[RU + u] - yl * hl;
 #pragma unroll
             for (int c = 0; c < KC; ++c)
@@ -935,9 +935,9 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         if (okl) {
             v1[rl] = vo;
             nacc = fma(vo, vo, nacc);
-            if (dl >= 0) ys[(int64_t)(dl - yb) * m + rl] = yo;
+            if (dl >= 0) ys[(int64_t)(dl - yb) * m + rl] = (Tb)yo;
         }
-        if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : yb7;
+        if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : (Tb)yb7;
     }
     const double nn = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
@@ -1029,12 +1029,12 @@ __global__ __launch_bounds__(256) void tcorr2_kernel(const State* __restrict__ s
 // FINAL = false: col = d, before an exact refresh of this step (skipped when
 // none is queued).  FINAL = true: col = (final d) - 1, after the loop; the
 // buffers of that step are chosen by the parity of col.
-template <int KC, int RU, bool FINAL, bool NT>
-__global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64_t ldy, int64_t m,
+template <int KC, int RU, bool FINAL, bool NT, typename Tb = double>
+__global__ __launch_bounds__(256) void ycol_kernel(Tb* __restrict__ Y, int64_t ldy, int64_t m,
                                                     const State* __restrict__ st, int d, int rows_per_blk,
                                                     const double* __restrict__ v1a, const double* __restrict__ v1b,
                                                     const double* __restrict__ h2a, const double* __restrict__ h2b,
-                                                    const double* __restrict__ ys) {
+                                                    const Tb* __restrict__ ys) {
     int col;
     if (FINAL) {
         if (st->stop == kStopError) return;
@@ -1058,16 +1058,7 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
     const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
     for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
         double y[RU][KC];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = rb + u;
-            const bool ok = r < r1;
-#pragma unroll
-            for (int c = 0; c < KC; ++c) {
-                const int k = lane + kWave * c;
-                y[u][c] = (ok && k < col) ? ld_y<NT>(y_src(Y, ldy, ys, m, r, k, yb)) : 0.0;
-            }
-        }
+        load_y_rows<NT, RU, KC>(y, Y, ldy, ys, m, rb, r1, lane, col, yb);
         double dot[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
@@ -1078,7 +1069,7 @@ __global__ __launch_bounds__(256) void ycol_kernel(double* __restrict__ Y, int64
         wave_sum_n<RU>(dot);
 #pragma unroll
         for (int u = 0; u < RU; ++u)
-            if (lane == u && rb + u < r1) Y[(rb + u) * ldy + col] = (v1[rb + u] - dot[u]) * inv;
+            if (lane == u && rb + u < r1) Y[(rb + u) * ldy + col] = (Tb)((v1[rb + u] - dot[u]) * inv);
         // the staged columns [yb, col) of these rows into Y
         if (ju < RU && rb + ju < r1 && yb + jj < col) Y[(rb + ju) * ldy + yb + jj] = ys[(int64_t)jj * m + rb + ju];
     }
@@ -1123,9 +1114,9 @@ typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr bool kResidPrefetchX = false;    // load the tile's X entries before the products (measured: slower, spills)
 #define RBD_RESID_MIN_BLOCKS 2                // workgroups per CU the register budget is sized for
 
-template <typename Tx, bool STORE = false>
+template <typename Tx, bool STORE = false, typename Ty = double>
 __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
-                                                          const double* __restrict__ Y, int64_t ldy, int K,
+                                                          const Ty* __restrict__ Y, int64_t ldy, int K,
                                                           const double* __restrict__ C, int64_t ldc,
                                                           const int* __restrict__ J,
                                                           const int* __restrict__ count_dev, int count_host,
@@ -1185,7 +1176,14 @@ __global__ __launch_bounds__(256, RBD_RESID_MIN_BLOCKS) void resid_mfma_kernel(c
                     const int rr = e / KB, kk = e % KB;
                     const int64_t row = row0 + rr;
                     const int k = k0 + kk;
-                    yr[q] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
+                    if constexpr (sizeof(Ty) == 8) {
+                        yr[q] = (row < rend && k < K) ? Y[row * ldy + k] : 0.0;
+                    } else {
+                        // clamped and unconditional, masked by a product (basis entries are
+                        // finite): a selected load would become a branch that waits for it
+                        const double v = (double)Y[min(row, rend - 1) * ldy + min(k, K - 1)];
+                        yr[q] = v * ((row < rend && k < K) ? 1.0 : 0.0);
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < CQ; ++q) {
@@ -1467,20 +1465,56 @@ __global__ __launch_bounds__(64 * kQuadGroups) void csr_quad_kernel(const double
 }
 
 // ---------------------------------------------------------------------------
+// read_stream: every 16-byte vector of a buffer read once (the X-scan's loads,
+// non-temporal when NT), values folded into a register and discarded.  The
+// bandwidth a scan of that buffer can reach.  Workgroups own contiguous
+// chunks; eight loads in flight per thread.
+// ---------------------------------------------------------------------------
+template <bool NT>
+__global__ __launch_bounds__(256) void read_stream_kernel(const u32x4* __restrict__ v, int64_t nvec,
+                                                          unsigned key, unsigned* __restrict__ sink) {
+    const int64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+    const int64_t a = (int64_t)blockIdx.x * per, b = min(nvec, a + per);
+    unsigned acc = 0u;
+    constexpr int U = 8;
+    int64_t i = a + threadIdx.x;
+    for (; i + (U - 1) * (int64_t)blockDim.x < b; i += U * (int64_t)blockDim.x) {
+        u32x4 r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const u32x4* q = v + i + u * (int64_t)blockDim.x;
+            r[u] = NT ? __builtin_nontemporal_load(q) : *q;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc ^= r[u].x ^ r[u].y ^ r[u].z ^ r[u].w;
+    }
+    for (; i < b; i += blockDim.x) {
+        const u32x4 r = v[i];
+        acc ^= r.x ^ r.y ^ r.z ^ r.w;
+    }
+    if (acc == key) *sink = acc;     // keeps the loads; practically never taken
+}
+
+// ---------------------------------------------------------------------------
 // epilogue: col_err = sqrt(e^2), zero unused columns/rows, publish d and status.
 // ---------------------------------------------------------------------------
 __global__ void epilogue_kernel(const State* __restrict__ st, const double* __restrict__ e2,
                                 double* __restrict__ col_err, int64_t n, double* __restrict__ Y, int64_t m,
                                 int d_max, double* __restrict__ T, int64_t* __restrict__ pivots,
                                 double* __restrict__ err_hist, int32_t* d_out, int32_t* status,
-                                int32_t* stop_reason) {
+                                int32_t* stop_reason, const float* __restrict__ Yf = nullptr) {
     const int d = st->d;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = gid; j < n; j += stride) col_err[j] = sqrt(e2[j]);
+    if (Yf) {                 // an FP32 basis: the output is its FP64 copy, zero beyond column d
+        const int64_t tot = m * (int64_t)d_max;
+        for (int64_t e = gid; e < tot; e += stride) Y[e] = (e % d_max) < d ? (double)Yf[e] : 0.0;
+    }
     if (d < d_max) {
-        for (int64_t i = gid; i < m; i += stride)
-            for (int k = d; k < d_max; ++k) Y[i * d_max + k] = 0.0;
+        if (!Yf)
+            for (int64_t i = gid; i < m; i += stride)
+                for (int k = d; k < d_max; ++k) Y[i * d_max + k] = 0.0;
         const int64_t tot = (int64_t)(d_max - d) * n;
         for (int64_t e = gid; e < tot; e += stride) T[(int64_t)d * n + e] = 0.0;
     }

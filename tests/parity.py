@@ -146,7 +146,8 @@ def _log(report, label):
 
 
 def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-8, exact_d: bool = True, weights=None,
-                norms=None, choice_rel: float = CHOICE_REL, eckart_young: bool = True, label: str = ""):
+                norms=None, choice_rel: float = CHOICE_REL, eckart_young: bool = True, label: str = "",
+                basis_tol: float = 1e-12):
     """dev: dict of numpy arrays (Y, T, pivots, col_err, err_hist, d); ref: OracleFit; X: stored values;
     weights: the diagonal of A when the errors are A-norms (eq. (3)), else None;
     norms: a callable giving the column A-norms of a matrix, for a general A."""
@@ -190,12 +191,14 @@ def compare_fit(dev, ref, X, rtol: float = 1e-5, gap: float = 1e-8, exact_d: boo
         out.append("final error differs: %.6e (d=%d) vs %.6e (d=%d)" % (Ed_dev, d, Ed_ref, ref.d))
 
     # 2. every step: a valid greedy choice against the device's own basis
-    out += _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young)
+    out += _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young,
+                                      basis_tol)
     _log(out, label)
     return out
 
 
-def _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young):
+def _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norms, ref, eckart_young,
+                               basis_tol=1e-12):
     msgs = []
     d = dev["d"]
     piv = dev["pivots"]
@@ -205,10 +208,10 @@ def _choice_and_invariant_msgs(out, dev, X, rtol, gap, choice_rel, weights, norm
     nx = np.linalg.norm(X, axis=0)
     if d:
         o = np.max(np.abs(Y.T @ Y - np.eye(d)))
-        if o > 1e-12:
+        if o > basis_tol:
             msgs.append(f"Y not orthonormal ({o:.2e})")
         dt = np.max(np.abs(T - Y.T @ X))
-        if dt > 1e-12 * max(nx.max(), 1e-300) * np.sqrt(X.shape[0]):
+        if dt > basis_tol * max(nx.max(), 1e-300) * np.sqrt(X.shape[0]):
             msgs.append(f"T != Y'X ({dt:.2e})")
     if len(set(piv[:d].tolist())) != d:
         msgs.append("repeated pivot")

@@ -218,3 +218,38 @@ def test_workspace_queries_over_many_shapes(lib, loop, monkeypatch):
         assert lib.rbd_classify_workspace_size(m, d, n, ctypes.byref(out)) == _lib.RBD_OK
         if d <= min(m, n):
             assert lib.rbd_reconstruct_backward_workspace_size(m, n, d, ctypes.byref(out)) == _lib.RBD_OK
+
+
+def test_fit_basis_queries_and_validation_without_device(lib, monkeypatch):
+    from paper_1503_05947_amd import _lib
+    monkeypatch.setenv("RBD_LOOP", "0")      # the FP32-basis plan never holds the persistent loop's buffers
+    out = ctypes.c_size_t(0)
+    for m, n, d in ((512, 256, 64), (1111, 777, 60), (1 << 20, 4096, 512)):
+        s64 = _lib.fit_workspace_size(m, n, d, _lib.RBD_BF16, _lib.RBD_BASIS_F64)
+        assert s64 == _lib.fit_workspace_size(m, n, d, _lib.RBD_BF16)
+        s32 = _lib.fit_workspace_size(m, n, d, _lib.RBD_BF16, _lib.RBD_BASIS_F32)
+        assert s32 >= s64 + 4 * m * d - 4096      # room for the FP32 basis (plan alignment aside)
+    assert lib.rbd_fit_basis_workspace_size(10, 10, 5, 0, 2, ctypes.byref(out)) == _lib.RBD_EINVAL
+    assert lib.rbd_fit_basis_workspace_size(10, 10, 5, 0, -1, ctypes.byref(out)) == _lib.RBD_EINVAL
+    fake = ctypes.c_void_p(4096)
+    ws = ctypes.c_void_p(1 << 20)
+
+    def call(basis, wsb=1 << 30, **kw):
+        a = dict(X=fake, xt=0, m=10, n=10, ldx=10, tol=0.0, mode=0, d_max=5, start=-1)
+        a.update(kw)
+        return lib.rbd_fit_basis(a["X"], a["xt"], a["m"], a["n"], a["ldx"], a["tol"], a["mode"], a["d_max"],
+                                 a["start"], basis, fake, fake, fake, fake, fake, fake, fake, None, ws, wsb, None)
+
+    assert call(2) == _lib.RBD_EINVAL
+    assert call(_lib.RBD_BASIS_F32, X=None) == _lib.RBD_EINVAL
+    assert call(_lib.RBD_BASIS_F32, ldx=9) == _lib.RBD_EINVAL
+    assert call(_lib.RBD_BASIS_F32, wsb=16) == _lib.RBD_EWORKSPACE
+
+
+def test_binding_rejects_bad_basis_choices():
+    import paper_1503_05947_amd as rbd
+    with pytest.raises(ValueError):
+        rbd.basis_code("f16")
+    with pytest.raises(ValueError):
+        import torch
+        rbd.FitBuffers(16, 16, 4, torch.float32, "cpu", spd=True, workspace=False, basis="f32")

@@ -102,3 +102,35 @@ def test_batched_deterministic_and_autotune():
             assert np.array_equal(x[k], y[k])
         ref = oracle.rbd_fit(v, 1e-6, 64, rel=True)
         assert compare_fit(x, ref, v) == []
+
+
+def config4_subbatch(count=12):
+    """Matrices of the 4096-matrix workload itself (sizes log-uniform in [64, 1024],
+    spectrum 10^(-i/8)): its four largest by m*n and eight spread over the rest."""
+    ms, ns = synth.batched_sizes(0, count=4096)
+    order = np.argsort(-(ms * ns), kind="stable")
+    idx = list(order[:4]) + list(order[np.linspace(4, len(order) - 1, count - 4).astype(int)])
+    mats, vals = [], []
+    for b in idx:
+        st, v = synth.quantize(synth.batched_matrix(0, int(b), int(ms[b]), int(ns[b])), "f32")
+        mats.append(st)
+        vals.append(v)
+    return idx, mats, vals
+
+
+@pytest.mark.parametrize("threads,wg", [(512, 1), (1024, 1)])
+def test_batched_parity_at_workload_sizes(threads, wg):
+    """m, n up to 1024, d_max 128, relative tol 1e-6, FP32: the batched workload's
+    own matrices (including its largest) against the oracle, under the autotuned
+    shape (512 threads, one workgroup per CU) and the widest one."""
+    import paper_1503_05947_amd as rbd
+    idx, mats, vals = config4_subbatch()
+    print(f"[gpu] batched workload sizes threads={threads} wg_per_cu={wg}: "
+          + ", ".join(f"{v.shape[0]}x{v.shape[1]}" for v in vals), flush=True)
+    res, _ = rbd.fit_batched([to_dev(s, "f32") for s in mats], tol=1e-6, d_max=128, rel=True,
+                             config=rbd.BatchConfig(threads, wg))
+    for b, r, v in zip(idx, res, vals):
+        ref = oracle.rbd_fit(v, 1e-6, 128, rel=True)
+        rep = compare_fit(host(r), ref, v)
+        print(f"[gpu]   matrix {b} {v.shape}: d={r.d} {rep.summary()}", flush=True)
+        assert rep == [], f"matrix {b} {v.shape}: " + "; ".join(rep)

@@ -26,7 +26,7 @@ import synth
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "parametric_1048576x4096_gram.json")
 
 
-def compare_with_gram_oracle(dtype, piv, hist, T, floor=1e-5, gap=1e-7, rtol=1e-5):
+def compare_with_gram_oracle(dtype, piv, hist, T, floor=1e-5, gap=1e-7, rtol=1e-5, hist_floor=None):
     """Returns (messages, steps compared pivot by pivot, steps of history compared)."""
     with open(GOLDEN) as f:
         g = json.load(f)["results"][dtype]
@@ -43,6 +43,8 @@ def compare_with_gram_oracle(dtype, piv, hist, T, floor=1e-5, gap=1e-7, rtol=1e-
         first = int(np.argmax(piv[:K] != np.array(g["pivots"][:K])))
         msgs.append(f"pivot {first} differs from the Gram-route oracle's")
         return msgs, K, resolved
+    if hist_floor is not None:            # compare the history only where E_k >= hist_floor * E_0
+        resolved = min(resolved, next((k for k in range(len(eh)) if eh[k] < hist_floor * E0), len(eh)))
     dh = np.max(np.abs(hist[:resolved] - eh[:resolved]))
     if dh > rtol * E0:
         msgs.append(f"error history differs from the oracle's by {dh / E0:.2e} E0")
@@ -199,3 +201,43 @@ def test_parametric_field_full_size_spd():
         jj = int(np.searchsorted(J, piv[k]))
         e_k = anorm((Xj[:, jj] - Y[:, :k] @ T[:k, piv[k]])[:, None])[0]
         assert abs(e_k - hist[k]) <= 1e-5 * E0, (k, e_k, hist[k])
+
+
+def test_parametric_field_full_size_bf16_basis_f32():
+    """BF16 storage with the basis kept in FP32: the Gram-route oracle's pivots
+    where its top two errors differ by more than 1e-5 E_0 and E_k >= 1e-2 E_0,
+    and its error history there to 1e-5 E_0 (the mode's indicator error is of
+    order 2^-24 E_0^2 / E_k); sampled columns as in the FP64-basis test."""
+    import torch
+
+    import paper_1503_05947_amd as rbd
+    print("[gpu] parametric field 1048576 x 4096 dtype=bf16 d_max=512 basis=f32", flush=True)
+    pf = synth.parametric_field(seed=0)
+    X = torch.empty((pf.m, pf.n), dtype=torch.bfloat16, device="cuda:0")
+    pf.fill_device(X)
+    res = rbd.fit(X, tol=0.0, d_max=512, basis="f32")
+    del X
+    torch.cuda.empty_cache()
+    assert res.d == 512 and res.stop == "dmax"
+    piv = res.pivots.cpu().numpy()
+    hist = res.err_hist.cpu().numpy()
+    col_err = res.col_err.cpu().numpy()
+    T = res.T.cpu().numpy()
+    E0 = hist[0]
+    msgs, K, resolved = compare_with_gram_oracle("bf16", piv, hist, T, floor=1e-2, gap=1e-5, hist_floor=1e-2)
+    print(f"[gpu] Gram-route oracle: {K} pivots compared, error history compared on {resolved} steps", flush=True)
+    assert msgs == [], "; ".join(msgs)
+    assert K >= 15
+    assert len(set(piv.tolist())) == 512
+    g = np.random.default_rng(7)
+    J = np.unique(np.concatenate([g.choice(pf.n, 5, replace=False), piv[[0, 1, 511]]]))
+    Xj = synth.quantize(pf.columns(J), "bf16")[1]
+    Y = res.Y.cpu().numpy()
+    nx = np.linalg.norm(Xj, axis=0)
+    assert np.max(np.abs(Y.T @ Xj - T[:, J]) / nx) <= 1e-6
+    true_err = np.linalg.norm(Xj - Y @ T[:, J], axis=0)
+    true_err[np.isin(J, piv)] = 0.0
+    assert np.max(np.abs(true_err - col_err[J])) <= max(1e-5, 2.0 ** -22 * E0 / hist[-1]) * E0
+    cols = [0, 1, 2, 255, 256, 509, 510, 511]
+    Gm = Y[:, cols].T @ Y[:, cols]
+    assert np.max(np.abs(Gm - np.eye(len(cols)))) <= 1e-6
