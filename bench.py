@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-basis32", action="store_true", help="skip the BF16 fit with the basis kept in FP32")
     ap.add_argument("--no-equal-error", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-examples", action="store_true",
+                    help="skip the fits of Table 3 and the section 4.2.2 field")
     ap.add_argument("--phases", action="store_true", help="extra profiled fit with a per-phase breakdown")
     ap.add_argument("--sample-cols", type=int, default=64)
     ap.add_argument("--no-next-rows", action="store_true",
@@ -527,7 +529,7 @@ def _with_driver(loop, fn):
             os.environ["RBD_LOOP"] = old
 
 
-def bump_field_section(rbd, K, W):
+def bump_field_section(rbd, K, W, cpu=True):
     """The 2048 x 2048 bump field (FP32), relative tol 1e-4 with d_max 256, and the
     same field in fixed-step mode (tol 0, all 256 steps): cache-resident, so the
     step time is latency, not HBM bandwidth.  The library runs such fits as one
@@ -557,11 +559,14 @@ def bump_field_section(rbd, K, W):
         r["graph_ms_per_fit"] = round(gsec * 1e3, 4)
         _, r1 = _with_driver("0", lambda: _time_fit(rbd, X, tol, rel, wl.d_max, reps, W))
         r["one_launch_per_kernel"] = r1
+        if cpu:
+            X64 = synth.quantize(wl.X, "f32")[1]
+            r["cpu_baseline"] = oracle_fit_time(X64, tol, rel, wl.d_max)
         out[name] = r
     return out
 
 
-def lowrank_section(rbd, K, W):
+def lowrank_section(rbd, K, W, cpu=True):
     """The 512 x 256 low-rank workload (FP32 storage, abs tol 1e-8, d_max 64)."""
     import torch
 
@@ -573,7 +578,74 @@ def lowrank_section(rbd, K, W):
     _, r1 = _with_driver("0", lambda: _time_fit(rbd, X, wl.tol, False, wl.d_max, reps, W))
     r["one_launch_per_kernel"] = r1
     r["workload"] = "low-rank spectrum 512x256 (sigma_i = 10^(-i/4), i < 32, + 1e-10 noise), FP32, tol 1e-8, d_max 64"
+    if cpu:
+        r["cpu_baseline"] = oracle_fit_time(synth.quantize(wl.X, "f32")[1], wl.tol, False, wl.d_max)
     return r
+
+
+def _host_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def oracle_fit_time(X64, tol, rel, d_max, sample_steps=None):
+    """The oracle (FP64 numpy, as it stands) on the stored values of a small
+    configuration, with the host's BLAS threads and with one thread.  With
+    sample_steps, a fit of that many steps is timed and scaled to the full
+    fit's step count (the oracle's step cost is about constant at these d)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    out = {"kind": "oracle", "threads": int(_host_threads())}
+
+    def run():
+        dm = sample_steps or d_max
+        t0 = time.perf_counter()
+        r = oracle.rbd_fit(X64, tol, dm, rel=rel)
+        return time.perf_counter() - t0, r.d
+
+    sec, d = run()
+    if sample_steps:
+        out["sample"] = f"{d} greedy steps timed, scaled to {d_max}"
+        sec *= d_max / max(d, 1)
+        d = d_max
+    out["greedy_steps"] = d
+    out["ms_per_fit"] = round(sec * 1e3, 2)
+    out["us_per_step"] = round(sec / max(d, 1) * 1e6, 1)
+    with threadpool_limits(limits=1):
+        sec1, d1 = run()
+    if sample_steps:
+        sec1 *= d_max / max(d1, 1)
+    out["single_thread_ms_per_fit"] = round(sec1 * 1e3, 2)
+    return out
+
+
+def paper_examples_section(rbd, K, W, cpu=True):
+    """The paper's worked examples on the device, beside the oracle: the three
+    separable functions of Table 3 (512^2 grid, FP64, relative tol 1e-10) and
+    the section 4.2.2 field (5001^2 grid, FP64, 22 steps)."""
+    import torch
+
+    import synth
+    out = {}
+    for which in (1, 2, 3):
+        X = synth.table3(which, 512)
+        Xd = torch.from_numpy(X).to("cuda:0")
+        _, r = _time_fit(rbd, Xd, 1e-10, True, 20, max(K, 1) * 10, W)
+        if cpu:
+            r["cpu_baseline"] = oracle_fit_time(X, 1e-10, True, 20)
+        out[f"table3_f{which}_512"] = r
+    X = synth.approx_field(5001)
+    Xd = torch.from_numpy(X).to("cuda:0")
+    _, r = _time_fit(rbd, Xd, 0.0, False, 22, max(K, 1), W)
+    if cpu:
+        r["cpu_baseline"] = oracle_fit_time(X, 0.0, False, 22)
+    out["approx_field_5001"] = r
+    del Xd
+    torch.cuda.empty_cache()
+    return out
 
 
 def stream_ceiling(rbd, t, reps=5):
@@ -620,11 +692,7 @@ def cpu_baseline(full_m, grid_sample=256, n=4096, steps=24):
     import numpy as np
     import oracle
     import synth
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = _host_threads()
     pf = synth.parametric_field(0, grid=grid_sample, n=n)
     X = synth.quantize(pf.full(), "f32")[1]
     m = X.shape[0]
@@ -807,10 +875,14 @@ def main():
                       "phases_ms_per_fit": {p: round(prof.phase_ms[p] / args.steps, 2) for p in _lib.PHASES}}
         del bufs, A
         torch.cuda.empty_cache()
+    cpu = not args.no_cpu_baseline
     log("bump field 2048 x 2048 (FP32)")
-    out["bump_field_2048"] = bump_field_section(rbd, args.steps, args.warmup)
+    out["bump_field_2048"] = bump_field_section(rbd, args.steps, args.warmup, cpu=cpu)
     log("low-rank 512 x 256 (FP32)")
-    out["lowrank_512x256"] = lowrank_section(rbd, args.steps, args.warmup)
+    out["lowrank_512x256"] = lowrank_section(rbd, args.steps, args.warmup, cpu=cpu)
+    if not args.no_paper_examples:
+        log("the paper's worked examples (Table 3, section 4.2.2)")
+        out["paper_examples"] = paper_examples_section(rbd, args.steps, args.warmup, cpu=cpu)
     if phases:
         out["phases"] = phases
     if not args.no_equal_error:

@@ -6,6 +6,8 @@
 // triangular with positive diagonal), and T = Y'X.  For L = <G, Y Y' X>:
 //   dL/dX        = Y (Y'G)                       (through T)
 //              + scatter_P( (Ybar + Y copyltu(M)) R^{-T} )   (through Y)
+// (scatter_P adds column k of its argument to column piv[k]; it runs inside
+// the product that writes Y (Y'G), so dX is written once.)
 //   Ybar = dL/dY = G T' + X (G'Y),   M = -Ybar' Y,
 //   copyltu(M)   = tril(M) + tril(M, -1)'
 // i.e. the standard adjoint of the QR factorisation with Rbar = 0.  Every
@@ -31,39 +33,88 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int
     return gemm_f64<TA, TB, TAe, TBe>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, part_elems, s);
 }
 
-// Rinv = R^{-1} (upper triangular, d x d row-major), R(i, k) = T(i, piv[k]) for i <= k.
-__global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int64_t* __restrict__ piv, int d,
-                            double* __restrict__ Rinv) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= d) return;
-    for (int i = j + 1; i < d; ++i) Rinv[(int64_t)i * d + j] = 0.0;
-    Rinv[(int64_t)j * d + j] = 1.0 / T[(int64_t)j * ldt + piv[j]];
-    for (int i = j - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) s = fma(T[(int64_t)i * ldt + piv[k]], Rinv[(int64_t)k * d + j], s);
-        Rinv[(int64_t)i * d + j] = -s / T[(int64_t)i * ldt + piv[i]];
+// Pivot ranks.  colrank[j], j = 0..n: the rank of column j among the pivots
+// ordered by column index when j is a pivot, else -1 - (the number of pivots
+// below j), so that the pivots among columns [a, b) have the ranks
+// [dec(colrank[a]), dec(colrank[b])) with dec(r) = r >= 0 ? r : -1 - r;
+// rank[k] = the rank of pivot k (ties, which distinct pivots never have, are
+// broken by position, so ranks are distinct).  One thread per column and per
+// pivot, the pivots staged in LDS.
+__global__ __launch_bounds__(256) void pivot_rank_kernel(const int64_t* __restrict__ piv, int d, int64_t n,
+                                                         int* __restrict__ colrank, int* __restrict__ rank) {
+    __shared__ int64_t ps[RBD_MAX_D];
+    for (int k = threadIdx.x; k < d; k += blockDim.x) ps[k] = piv[k];
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j <= n) {
+        int lb = 0;
+        bool hit = false;
+        for (int i = 0; i < d; ++i) {
+            lb += ps[i] < j;
+            hit |= ps[i] == j;
+        }
+        colrank[j] = (hit && j < n) ? lb : -1 - lb;
+    }
+    if (j < d) {
+        const int64_t pj = ps[j];
+        int r = 0;
+        for (int i = 0; i < d; ++i) r += (ps[i] < pj) || (ps[i] == pj && i < j);
+        rank[j] = r;
     }
 }
 
-// The same inverse for d <= kRinvLds: one wave per column j of Rinv, solving
-// R x = e_j by back substitution.  Lane l keeps x(l) and x(l + 64) in
-// registers; each step i is one wave sum of R(i, k) x(k) over k in (i, j],
-// times 1 / R(i, i).  R's upper triangle is staged in LDS once per workgroup,
-// packed by rows (row i holds columns i..d-1 at tri_off(i)), with the
-// reciprocals of its diagonal after it.
+// Rinv' = R^{-1} with its rows in pivot-rank order: row rank[k] holds row k
+// of R^{-1} (R upper triangular, d x d, R(i, k) = T(i, piv[k]) for i <= k).
+// Then column rank[k] of Ybar Rinv'^T is column k of Ybar R^{-T}, so the
+// columns that a tile of dX gains are contiguous.
+__global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int64_t* __restrict__ piv, int d,
+                            const int* __restrict__ rank, double* __restrict__ Rinv) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= d) return;
+    for (int i = j + 1; i < d; ++i) Rinv[(int64_t)rank[i] * d + j] = 0.0;
+    Rinv[(int64_t)rank[j] * d + j] = 1.0 / T[(int64_t)j * ldt + piv[j]];
+    for (int i = j - 1; i >= 0; --i) {
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k) s = fma(T[(int64_t)i * ldt + piv[k]], Rinv[(int64_t)rank[k] * d + j], s);
+        Rinv[(int64_t)rank[i] * d + j] = -s / T[(int64_t)i * ldt + piv[i]];
+    }
+}
+
+// The same inverse for d <= kRinvLds: one wave per column j of R^{-1}, solving
+// R x = e_j by column-oriented back substitution: for i = j down to 0,
+// x_i = b_i / R(i, i), then b_k -= R(k, i) x_i for k < i.  Lane l keeps rows l
+// and l + 64 of b (then x) in registers; a step is one lane broadcast and one
+// multiply-add per row, with no cross-lane sum.  R's upper triangle is staged
+// in LDS once per workgroup, packed by columns (column i holds rows 0..i at
+// i (i + 1) / 2), with the reciprocals of its diagonal after it; the staging
+// loads go out in groups of 32 from clamped addresses (a load under the
+// triangle test would wait for its data before the next one issues).
 constexpr int kRinvLds = 128;
-__device__ __forceinline__ int tri_off(int i, int d) { return i * d - i * (i - 1) / 2; }
 __global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
                                                        const int64_t* __restrict__ piv, int d,
-                                                       double* __restrict__ Rinv) {
-    extern __shared__ double Rp[];           // packed R: d (d + 1) / 2, then 1 / R(i, i): d
-    double* rd = Rp + d * (d + 1) / 2;
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {      // independent loads, all in flight
-        const int i = e / d, k = e % d;
-        if (k >= i) {
-            const double v = T[(int64_t)i * ldt + piv[k]];
-            Rp[tri_off(i, d) + k - i] = v;
-            if (k == i) rd[i] = 1.0 / v;
+                                                       const int* __restrict__ rank, double* __restrict__ Rinv) {
+    extern __shared__ double Rc[];           // packed R by columns: d (d + 1) / 2, then 1 / R(i, i): d
+    __shared__ int64_t ps[kRinvLds];
+    double* rd = Rc + d * (d + 1) / 2;
+    for (int k = threadIdx.x; k < d; k += blockDim.x) ps[k] = piv[k];
+    __syncthreads();
+    constexpr int U = 32;
+    for (int e0 = threadIdx.x; e0 < d * d; e0 += U * blockDim.x) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = min(e0 + u * (int)blockDim.x, d * d - 1);
+            const int k = e / d, i = e % d;
+            v[u] = T[(int64_t)min(k, i) * ldt + ps[i]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * (int)blockDim.x;
+            const int k = e / d, i = e % d;
+            if (e < d * d && k <= i) {
+                Rc[i * (i + 1) / 2 + k] = v[u];
+                if (k == i) rd[i] = 1.0 / v[u];
+            }
         }
     }
     __syncthreads();
@@ -71,33 +122,20 @@ __global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict_
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= d) return;                      // whole waves leave together
     const int k0 = lane, k1 = lane + kWave;
-    double x0 = (k0 == j) ? rd[j] : 0.0;
-    double x1 = (k1 == j) ? rd[j] : 0.0;
-    for (int i = j - 1; i >= 0; --i) {
-        const double* ri = Rp + tri_off(i, d) - i;             // ri[k] = R(i, k), k >= i
-        double sum = 0.0;
-        if (k0 > i && k0 <= j) sum = ri[k0] * x0;
-        if (k1 > i && k1 <= j) sum = fma(ri[k1], x1, sum);
-        sum = wave_sum(sum);
-        const double v = -sum * rd[i];
-        if (k0 == i) x0 = v;
-        if (k1 == i) x1 = v;
+    double x0 = (k0 == j) ? 1.0 : 0.0;
+    double x1 = (k1 == j) ? 1.0 : 0.0;
+    for (int i = j; i >= 0; --i) {
+        const double* ci = Rc + i * (i + 1) / 2;               // ci[k] = R(k, i), k <= i
+        const double src = i < kWave ? x0 : x1;                // i is uniform
+        const int lo = __builtin_amdgcn_readlane(__double2loint(src), i % kWave);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(src), i % kWave);
+        const double xi = __hiloint2double(hi, lo) * rd[i];
+        const double r0 = ci[min(k0, i)], r1 = ci[min(k1, i)];
+        x0 = k0 == i ? xi : (k0 < i ? fma(-r0, xi, x0) : x0);
+        x1 = k1 == i ? xi : (k1 < i ? fma(-r1, xi, x1) : x1);
     }
-    if (k0 < d) Rinv[(int64_t)k0 * d + j] = x0;
-    if (k1 < d) Rinv[(int64_t)k1 * d + j] = x1;
-}
-
-// dX(:, piv[k]) += Abar(:, k)   (pivots are distinct; one outside [0, n) is skipped)
-__global__ void scatter_add_cols_kernel(const double* __restrict__ Abar, int64_t m, int d,
-                                        const int64_t* __restrict__ piv, int64_t n, double* __restrict__ dX,
-                                        int64_t lddx) {
-    const int64_t tot = m * d;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / d;
-        const int k = (int)(e % d);
-        const int64_t c = piv[k];
-        if (c >= 0 && c < n) dX[i * lddx + c] += Abar[e];
-    }
+    if (k0 < d) Rinv[(int64_t)rank[k0] * d + j] = x0;
+    if (k1 < d) Rinv[(int64_t)rank[k1] * d + j] = x1;
 }
 
 // S = tril(M) + tril(M, -1)'
@@ -109,7 +147,7 @@ __global__ void copyltu_kernel(const double* __restrict__ Mm, int d, double* __r
 }
 
 struct BwdPlan {
-    size_t o_c1, o_ybar, o_m, o_s, o_rinv, o_abar, o_part, total;
+    size_t o_c1, o_ybar, o_m, o_s, o_rinv, o_abar, o_colrank, o_rank, o_part, total;
 };
 
 bool make_bwd_plan(int64_t m, int64_t n, int32_t d, BwdPlan* P) {
@@ -126,6 +164,8 @@ bool make_bwd_plan(int64_t m, int64_t n, int32_t d, BwdPlan* P) {
     P->o_s = take(8 * (size_t)d * d);
     P->o_rinv = take(8 * (size_t)d * d);
     P->o_abar = take(8 * (size_t)m * d);
+    P->o_colrank = take(4 * ((size_t)n + 1));
+    P->o_rank = take(4 * (size_t)d);
     P->o_part = take(8 * kPartElems);
     P->total = o;
     return true;
@@ -142,11 +182,12 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     double* Rinv = reinterpret_cast<double*>(ws + P.o_rinv);
     double* Abar = reinterpret_cast<double*>(ws + P.o_abar);
     double* part = reinterpret_cast<double*>(ws + P.o_part);
+    int* colrank = reinterpret_cast<int*>(ws + P.o_colrank);
+    int* rank = reinterpret_cast<int*>(ws + P.o_rank);
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    // C1 = Y'G (d x n);  dX = Y C1
+    // C1 = Y'G (d x n)
     ok(gemm<true, false, double, Tg>(d, n, m, 1.0, Y, ldy, G, ldg, 0.0, C1, n, part, kPartElems, s));
-    ok(gemm<false, false, double, double>(m, n, d, 1.0, Y, ldy, C1, n, 0.0, dX, lddx, nullptr, 0, s));
     // Ybar = G T' + X C1'  (m x d)
     ok(gemm<false, true, Tg, double>(m, d, n, 1.0, G, ldg, T, ldt, 0.0, Ybar, d, part, kPartElems, s));
     ok(gemm<false, true, Tx, double>(m, d, n, 1.0, X, ldx, C1, n, 1.0, Ybar, d, part, kPartElems, s));
@@ -155,20 +196,23 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     copyltu_kernel<<<(unsigned)cd((int64_t)d * d, 256), 256, 0, s>>>(Mm, d, S);
     ok(hipGetLastError());
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
-    // Abar = Ybar R^{-T};  dX(:, P) += Abar
+    // Abar' = Ybar R^{-T} with its columns in pivot-rank order
+    pivot_rank_kernel<<<(unsigned)cd(std::max<int64_t>(n + 1, d), 256), 256, 0, s>>>(piv, d, n, colrank, rank);
+    ok(hipGetLastError());
     if (d <= kRinvLds) {
         const size_t lds = sizeof(double) * ((size_t)d * (d + 1) / 2 + d);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(T, ldt, piv, d, Rinv);
+        rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(T, ldt, piv, d, rank, Rinv);
     } else {
-        rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, Rinv);
+        rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, rank, Rinv);
     }
     ok(hipGetLastError());
     ok(gemm<false, true, double, double>(m, d, d, 1.0, Ybar, d, Rinv, d, 0.0, Abar, d, nullptr, 0, s));
-    scatter_add_cols_kernel<<<(unsigned)std::min<int64_t>(4096, cd(m * d, 256)), 256, 0, s>>>(Abar, m, d, piv, n, dX,
-                                                                                              lddx);
-    ok(hipGetLastError());
+    // dX = Y C1 + scatter_P(Abar): each tile of dX adds the Abar' columns of the pivots among its
+    // columns as extra k-steps of its own product (dX is written once)
+    ok(gemm_f64<false, false, double, double>(m, n, d, 1.0, Y, ldy, C1, n, 0.0, dX, lddx, nullptr, 0, s,
+                                              GemmColAdd{Abar, d, colrank}));
     return e == hipSuccess ? RBD_OK : RBD_EDEVICE;
 }
 

@@ -18,6 +18,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "rbd_device.h"
 
@@ -25,23 +26,51 @@ namespace rbd {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kGM = 128, kGN = 128, kGK = 16;
+constexpr int kGN = 128, kGK = 16;
+constexpr int64_t kShortK = 256;      // k ranges up to this use the 64-row tiles when they make >= 1024 tiles
 
-template <bool TA, bool TB, typename TAe, typename TBe>
-__global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                        const TAe* __restrict__ A, int64_t lda,
-                                                        const TBe* __restrict__ B, int64_t ldb, double beta,
-                                                        double* __restrict__ C, int64_t ldc, int64_t kchunk,
-                                                        double* __restrict__ part) {
+// WM: rows of each wave's sub-tile (64, or 32 for short k ranges: half the
+// accumulators, so three workgroups per CU instead of two hide the prologue
+// and the epilogue of each other's tiles).
+template <int WM>
+struct GemmShape {
+    static constexpr int GM = 2 * WM;              // workgroup tile rows
+    static constexpr int MT = WM / 16;             // MFMA tiles per wave along M
+    static constexpr int WG_PER_CU = WM == 64 ? 2 : 3;
+};
+
+// Optional extra columns of the product (single-split products only):
+// C += A2 E, where E (n2 x N) is one in row colrank[j] of column j when
+// colrank[j] >= 0 and zero elsewhere, i.e. output column j gains column
+// colrank[j] of A2 (M x n2, leading dimension ld2).  colrank has N + 1 entries
+// and is increasing in the sense that a column's rank, or -1 - (its insertion
+// point) for columns that gain nothing, never decreases with j, so a tile's
+// columns gain the contiguous range of A2's columns [lo, hi) decoded from
+// colrank[col0] and colrank[col0 + 128]: they run as extra k-steps of the
+// tile, with E generated in place.  Products by exact zeros and ones add
+// nothing else, so each gaining entry is (A B)(i, j) + A2(i, colrank[j]) with
+// one rounding.
+struct GemmColAdd {
+    const double* a2 = nullptr;
+    int64_t ld2 = 0;
+    const int* colrank = nullptr;
+};
+
+template <bool TA, bool TB, typename TAe, typename TBe, int WM = 64, bool ADD = false>
+__global__ __launch_bounds__(256, GemmShape<WM>::WG_PER_CU) void gemm_f64_kernel(
+    int64_t M, int64_t N, int64_t K, double alpha, const TAe* __restrict__ A, int64_t lda,
+    const TBe* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc, int64_t kchunk,
+    double* __restrict__ part, GemmColAdd add) {
+    constexpr int kGM = GemmShape<WM>::GM, MT = GemmShape<WM>::MT;
     __shared__ double As[kGK][kGM + 1];
     __shared__ double Bs[kGK][kGN + 1];
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;       // this wave's 64 x 64 sub-tile
+    const int wr = (w >> 1) * WM, wc = (w & 1) * 64;       // this wave's WM x 64 sub-tile
     const int64_t row0 = (int64_t)blockIdx.y * kGM, col0 = (int64_t)blockIdx.x * kGN;
     const int64_t kb = (int64_t)blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-    f64x4 acc[4][4];
+    f64x4 acc[MT][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
@@ -72,6 +101,26 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
             rb[q] = (gj < N && gk < ke) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : TBe{};
         }
     };
+    // the extra columns (see GemmColAdd): A2's first chunk is loaded into the A
+    // registers during the last chunk of the product, like any next chunk
+    constexpr bool kPrefetchAdd = ADD && !TA && std::is_same<TAe, double>::value;
+    auto dec = [](int r) { return r >= 0 ? r : -1 - r; };
+    int lo = 0, hi = 0;
+    if (ADD) {
+        lo = dec(add.colrank[min(col0, N)]);
+        hi = dec(add.colrank[min(col0 + kGN, N)]);
+    }
+    auto load_add = [&](int k0) {       // A2(row0 .. row0 + kGM - 1, k0 .. k0 + kGK - 1), zero past hi
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + 256 * q;
+            const int i = e / kGK, k = e % kGK;
+            const int64_t gi = row0 + i;
+            const double v = (gi < M && k0 + k < hi) ? add.a2[gi * add.ld2 + k0 + k] : 0.0;
+            if constexpr (kPrefetchAdd) ra[q] = v;
+            else As[k][i] = v;
+        }
+    };
     if (kb < ke) load(kb);
     for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
         __syncthreads();      // the previous chunk's products are done with LDS
@@ -89,23 +138,72 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(int64_t M, int64_t N, 
         }
         __syncthreads();
         if (k0 + kGK < ke) load(k0 + kGK);
+        else if (kPrefetchAdd && lo < hi) load_add(lo);
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
-            double af[4], bf[4];
+            double af[MT], bf[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) af[a] = As[ks + lane / 16][wr + a * 16 + lane % 16];
+            for (int a = 0; a < MT; ++a) af[a] = As[ks + lane / 16][wr + a * 16 + lane % 16];
 #pragma unroll
             for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + lane / 16][wc + b * 16 + lane % 16];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < MT; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
     }
+    if (ADD) {
+        // this wave's 64 columns gain [lo_w, hi_w): it multiplies only the k-steps that meet it
+        const int lo_w = dec(add.colrank[min(col0 + wc, N)]), hi_w = dec(add.colrank[min(col0 + wc + 64, N)]);
+        for (int k0 = lo; k0 < hi; k0 += kGK) {
+            const bool pre = kPrefetchAdd && k0 == lo && kb < ke;      // already in ra
+            __syncthreads();
+            if (pre) {
+#pragma unroll
+                for (int q = 0; q < QA; ++q) {
+                    const int e = tid + 256 * q;
+                    As[e % kGK][e / kGK] = Ld<TAe>::from(ra[q]);
+                }
+            } else {
+                if constexpr (kPrefetchAdd) {
+                    load_add(k0);
+#pragma unroll
+                    for (int q = 0; q < QA; ++q) {
+                        const int e = tid + 256 * q;
+                        As[e % kGK][e / kGK] = Ld<TAe>::from(ra[q]);
+                    }
+                } else {
+                    load_add(k0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < (kGN * kGK) / 256; ++q) {
+                const int e = tid + 256 * q;
+                const int k = e / kGN, j = e % kGN;
+                const int64_t gj = col0 + j;
+                Bs[k][j] = (gj < N && add.colrank[gj] == k0 + k) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kGK; ks += 4) {
+                if (k0 + ks + 4 <= lo_w || k0 + ks >= hi_w) continue;      // wave-uniform
+                double af[MT], bf[4];
+#pragma unroll
+                for (int a = 0; a < MT; ++a) af[a] = As[ks + lane / 16][wr + a * 16 + lane % 16];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + lane / 16][wc + b * 16 + lane % 16];
+#pragma unroll
+                for (int a = 0; a < MT; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
     double* out = part ? part + (int64_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -155,17 +253,34 @@ constexpr size_t kPartElems = (size_t)8 << 20;   // split-k partials: 64 MB
 template <bool TA, bool TB, typename TAe, typename TBe>
 inline hipError_t gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int64_t lda, const TBe* B,
                            int64_t ldb, double beta, double* C, int64_t ldc, double* part, size_t part_elems,
-                           hipStream_t s) {
+                           hipStream_t s, GemmColAdd add = {}) {
     auto cdiv = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    constexpr int kGM = GemmShape<64>::GM;
     const int64_t tiles = cdiv(M, kGM) * cdiv(N, kGN);
     int64_t splits = 1;
-    while (part && tiles * splits < 512 && K / (splits * 2) >= 256 && (size_t)(splits * 2) * M * N <= part_elems)
+    while (part && !add.a2 && tiles * splits < 512 && K / (splits * 2) >= 256 && (size_t)(splits * 2) * M * N <= part_elems)
         splits *= 2;
     const int64_t kchunk = cdiv(cdiv(K, splits), kGK) * kGK;
     splits = std::max<int64_t>(1, cdiv(K, kchunk));
+    if (splits == 1 && K <= kShortK && tiles >= 1024) {
+        // a short k range over many tiles: 64 x 128 tiles, three workgroups per CU
+        constexpr int gm = GemmShape<32>::GM;
+        const dim3 grid((unsigned)cdiv(N, kGN), (unsigned)cdiv(M, gm), 1u);
+        if (add.a2)
+            gemm_f64_kernel<TA, TB, TAe, TBe, 32, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C,
+                                                                          ldc, kchunk, nullptr, add);
+        else
+            gemm_f64_kernel<TA, TB, TAe, TBe, 32><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                        kchunk, nullptr, add);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)cdiv(N, kGN), (unsigned)cdiv(M, kGM), (unsigned)splits);
-    gemm_f64_kernel<TA, TB, TAe, TBe><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
-                                                            splits > 1 ? part : nullptr);
+    if (add.a2)
+        gemm_f64_kernel<TA, TB, TAe, TBe, 64, true><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                                                                      kchunk, nullptr, add);
+    else
+        gemm_f64_kernel<TA, TB, TAe, TBe><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
+                                                                splits > 1 ? part : nullptr, add);
     if (splits > 1) {
         const int64_t tot = M * N;
         gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(tot, 256)), 256, 0, s>>>(

@@ -43,6 +43,24 @@ def test_backward_matches_oracle(xdt, gdt):
     assert np.max(np.abs(grad - ref)) <= 1e-9 * scale
 
 
+@pytest.mark.parametrize("m,n,d", [(1111, 777, 200), (517, 300, 128), (333, 129, 129), (2000, 3, 3)])
+def test_backward_ragged_shapes_and_both_inverses(m, n, d):
+    """Shapes off the 128 x 128 tiles, d on both sides of the LDS inverse's limit
+    (128), pivots reaching the last columns: the pivot columns are added inside
+    the tiles of dX that hold them."""
+    import paper_1503_05947_amd as rbd
+    print(f"[gpu] backward ragged m={m} n={n} d={d}", flush=True)
+    w = synth.bump_field(9, m=m, n=n, noise=1e-2)
+    Xs, Xv = synth.quantize(w.X, "f32")
+    res = rbd.fit(dev(Xs, "f32"), tol=0.0, d_max=d)
+    assert res.d == d
+    P = res.pivots.cpu().numpy()
+    G = synth.cotangent(3, m, n)
+    grad = rbd.reconstruct_backward(dev(Xs, "f32"), dev(G), res.Y, res.T, res.pivots).cpu().numpy()
+    ref = oracle.reconstruction_grad(Xv, P, G)
+    assert np.max(np.abs(grad - ref)) <= 1e-9 * np.abs(ref).max()
+
+
 def test_backward_finite_differences_on_device_gradient():
     import paper_1503_05947_amd as rbd
     print("[gpu] backward vs central differences", flush=True)
