@@ -56,9 +56,9 @@ typedef enum RBD_ENUM_BASE {
 } rbd_dtype;
 
 /* Storage of the basis while a fit runs (rbd_fit_basis).  RBD_BASIS_F64 is
- * rbd_fit's.  RBD_BASIS_F32 keeps Y in FP32 in the workspace (half the bytes
- * of the pass over Y each step), with all arithmetic still FP64, and writes
- * its FP64 copy to the output Y at the end. */
+ * rbd_fit's.  RBD_BASIS_F32 keeps Y in FP32 in the workspace once the fit
+ * passes 128 columns (half the bytes of the pass over Y each step), with all
+ * arithmetic still FP64, and writes its FP64 copy to the output Y at the end. */
 typedef enum RBD_ENUM_BASE { RBD_BASIS_F64 = 0, RBD_BASIS_F32 = 1 } rbd_basis;
 
 /* How `tol` is read: RBD_TOL_ABS uses tau = tol, RBD_TOL_REL uses
@@ -134,18 +134,22 @@ int rbd_fit(const void* X, rbd_dtype xt, int64_t m, int64_t n, int64_t ldx,
 /*
  * rbd_fit_basis -- rbd_fit with a choice of how the basis is stored while
  * the loop runs (rbd_fit_basis(..., RBD_BASIS_F64, ...) is rbd_fit).  With
- * RBD_BASIS_F32 every basis vector xi_k is formed in FP64 as by rbd_fit and
- * stored rounded to FP32; the Gram-Schmidt passes and the exact refreshes
- * read the stored (rounded) vectors, while the row T(k, :) is formed from
- * the FP64 vector before rounding.  The output Y holds the stored values
- * (orthonormal to about 1e-7 instead of 1e-15).  The
+ * RBD_BASIS_F32 inputs small enough for rbd_fit's single-launch loop (X of at
+ * most 64 MB, whose passes read the caches, not HBM) run exactly as rbd_fit;
+ * otherwise the first 128 steps run exactly as rbd_fit's (a fit that ends
+ * within 128 columns gives rbd_fit's results); when the fit passes 128
+ * columns the basis is rounded to FP32, and every later basis vector xi_k is
+ * formed in FP64 as by rbd_fit and stored rounded to FP32.  From then on the
+ * Gram-Schmidt passes and the exact refreshes read the stored (rounded)
+ * vectors, while the row T(k, :) is formed from the FP64 vector before
+ * rounding.  The output Y holds the stored values (for fits past 128
+ * columns, orthonormal to about 1e-7 instead of 1e-15).  The
  * downdated errors then carry, between exact refreshes, an absolute error of
  * order 2^-24 ||x_j||^2 / e_j in e_j (the rounded basis is orthonormal only
  * to FP32 precision), so the mode is meant for data whose errors stay well
  * above 2^-12 ||x_j||: BF16 storage (unit roundoff 2^-9), whose fits it
  * speeds up by halving the bytes of the pass over Y.  The exact refreshes and
- * their trigger are those of rbd_fit.  The persistent single-launch loop is
- * not used in this mode.
+ * their trigger are those of rbd_fit.
  *   basis       RBD_BASIS_F64 or RBD_BASIS_F32; other arguments as for rbd_fit.
  *   workspace   at least rbd_fit_basis_workspace_size() bytes.
  * Returns what rbd_fit returns; RBD_EINVAL for an unknown `basis`.

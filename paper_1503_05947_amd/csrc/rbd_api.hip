@@ -59,6 +59,7 @@ struct FitPlan {
     bool loop = false;
     bool y32 = false;           // the basis is kept in FP32 (o_yf) and copied out at the end
     size_t o_yf = 0;
+    int64_t ldyf = 0;           // its leading dimension: d_max rounded up to even (8-byte column pairs)
     int lp_G = 0, lp_Gc = 0, lp_RB = 0, lp_CW = 0;
     size_t o_lp_bv = 0, o_lp_bi = 0, o_lp_bc = 0, o_lp_part = 0, o_lp_qc = 0, o_lp_ql = 0, o_lp_rp = 0;
     // workspace offsets (bytes)
@@ -162,8 +163,7 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
     P->rf_grid = (int)cdiv(n, 256);
 
     P->ntickets = (int)std::max<int64_t>(P->up_ncb + 1, P->cg_ngroups + 1) + 8;
-    if (!P->y32) plan_loop(P);
-    else P->loop = false;
+    plan_loop(P);            // inputs the persistent loop takes keep the FP64 basis in every mode
 
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -199,7 +199,10 @@ bool make_fit_plan(int64_t m, int64_t n, int32_t d_max, rbd_dtype xt, FitPlan* P
         std::max<size_t>(((size_t)P->up_SG + kp_max + 1) * 2 * n, (size_t)P->cg_ngroups * std::max(P->D, 1));
     P->o_l2 = take(8 * l2_elems);
     P->o_rpart = take(8 * (size_t)P->rc_S * n);
-    if (P->y32) P->o_yf = take(4 * (size_t)m * d_max);
+    if (P->y32) {
+        P->ldyf = d_max + (d_max & 1);
+        P->o_yf = take(4 * (size_t)m * P->ldyf);
+    }
     if (P->loop) {
         P->o_lp_bv = take(8 * 2 * (size_t)P->lp_G);
         P->o_lp_bi = take(8 * 2 * (size_t)P->lp_G);
@@ -366,17 +369,34 @@ void launch_gvec2(const FitPlan& P, double* Y, const State* st, int d, const dou
                                                                             hw, w, ys, v2, g);
 }
 
+// rbd_fit_basis(RBD_BASIS_F32): steps below this column run on the FP64 basis
+// (a multiple of 128, so the switch falls on a block boundary).
+constexpr int kY32Switch = 128;
+
+// The FP32-basis passes: two columns per lane, KC / 2 chunks of 128 columns.
+constexpr int kc2_of(int KC) { return KC <= 2 ? 1 : KC / 2; }
+constexpr int rows32(int KC) { return kc2_of(KC) <= 2 ? 8 : (kc2_of(KC) <= 4 ? 4 : 2); }
+
 template <int KC, typename Tb>
 void launch_cgs1_lag(const FitPlan& P, const double* xp, Tb* Y, const double* T, State* st, int d,
-                     const double* v1p, const double* h2p, double* v1, Tb* ys, double* part, hipStream_t s) {
-    if (y_stream(P, d))
+                     const double* v1p, const double* h2p, double* v1, double* ys, double* part, hipStream_t s) {
+    if constexpr (std::is_same<Tb, float>::value) {
+        constexpr int K2 = kc2_of(KC), R2 = rows32(KC);
+        if (y_stream(P, d))
+            cgs1_lag32_kernel<K2, R2, true><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.ldyf, T, P.n, st, d, P.cg_rows, v1p,
+                                                                    h2p, v1, ys, part, std::max(P.D, 1));
+        else
+            cgs1_lag32_kernel<K2, R2, false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.ldyf, T, P.n, st, d, P.cg_rows, v1p,
+                                                                     h2p, v1, ys, part, std::max(P.D, 1));
+    } else if (y_stream(P, d)) {
         cgs1_lag_kernel<KC, rows_in_flight(KC), true, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
                                                                               P.cg_rows, v1p, h2p, v1, ys, part,
                                                                               std::max(P.D, 1));
-    else
+    } else {
         cgs1_lag_kernel<KC, rows_in_flight(KC), false, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
                                                                                P.cg_rows, v1p, h2p, v1, ys, part,
                                                                                std::max(P.D, 1));
+    }
 }
 
 template <typename Tx>
@@ -387,19 +407,28 @@ void launch_gather(const FitPlan& P, const Tx* X, int64_t ldx, const State* st, 
 
 template <int KC, bool FINAL, typename Tb>
 void launch_ycol(const FitPlan& P, Tb* Y, const State* st, int d, const double* v1a, const double* v1b,
-                 const double* h2a, const double* h2b, const Tb* ys, hipStream_t s) {
-    // FINAL: the column index is only known on the device; size the choice by D
-    if (y_stream(P, FINAL ? P.D : d))
+                 const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
+    if constexpr (std::is_same<Tb, float>::value) {
+        constexpr int K2 = kc2_of(KC), R2 = rows32(KC);
+        if (y_stream(P, FINAL ? P.D : d))
+            ycol32_kernel<K2, R2, FINAL, true><<<P.cg_S, 256, 0, s>>>(Y, P.ldyf, P.m, st, d, P.cg_rows, v1a, v1b,
+                                                                       h2a, h2b, ys);
+        else
+            ycol32_kernel<K2, R2, FINAL, false><<<P.cg_S, 256, 0, s>>>(Y, P.ldyf, P.m, st, d, P.cg_rows, v1a, v1b,
+                                                                        h2a, h2b, ys);
+    } else if (y_stream(P, FINAL ? P.D : d)) {
+        // FINAL: the column index is only known on the device; size the choice by D
         ycol_kernel<KC, rows_in_flight(KC), FINAL, true, Tb><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
                                                                                  v1a, v1b, h2a, h2b, ys);
-    else
+    } else {
         ycol_kernel<KC, rows_in_flight(KC), FINAL, false, Tb><<<P.cg_S, 256, 0, s>>>(Y, P.d_max, P.m, st, d, P.cg_rows,
                                                                                   v1a, v1b, h2a, h2b, ys);
+    }
 }
 
 template <bool FINAL, typename Tb>
 void launch_ycol_kc(int kc, const FitPlan& P, Tb* Y, const State* st, int d, const double* v1a,
-                    const double* v1b, const double* h2a, const double* h2b, const Tb* ys, hipStream_t s) {
+                    const double* v1b, const double* h2a, const double* h2b, const double* ys, hipStream_t s) {
     switch (kc) {
         case 1: launch_ycol<1, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
         case 2: launch_ycol<2, FINAL, Tb>(P, Y, st, d, v1a, v1b, h2a, h2b, ys, s); break;
@@ -522,21 +551,21 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     double* const h2s[2] = {h2, h2 + RBD_MAX_D + 1};
     // the basis is kept in Y itself, or in FP32 in the workspace (copied out by the epilogue)
     float* const Yf = P.y32 ? reinterpret_cast<float*>(ws + P.o_yf) : nullptr;
-    auto identity_steps = [&](auto* Yb) -> int {
+    auto identity_steps = [&](auto* Yb, int d0, int d1) -> int {
     using Tb = std::remove_pointer_t<decltype(Yb)>;
-    Tb* const ysb = reinterpret_cast<Tb*>(ys);          // staged slots in the basis' storage type
-    for (int d = 0; d < P.D; ++d) {
+    const int64_t ldb = std::is_same<Tb, float>::value ? P.ldyf : P.d_max;
+    for (int d = d0; d < d1; ++d) {
         const int c = d & 1;
         const int kc = kc_for(d);
         prof_begin(RBD_PHASE_CGS1, s);
         launch_gather<Tx>(P, X, ldx, st, xp, s);
         RBD_LAUNCH_CHECK();
         switch (kc) {
-            case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
-            case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
-            case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
-            case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
-            default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ysb, part, s); break;
+            case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
         }
         RBD_LAUNCH_CHECK();
         launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
@@ -564,9 +593,9 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         prof_end(RBD_PHASE_UPDATE, s);
         prof_begin(RBD_PHASE_RESID, s);
         // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
-        launch_ycol_kc<false>(kc, P, Yb, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ysb, s);
+        launch_ycol_kc<false>(kc, P, Yb, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
         RBD_LAUNCH_CHECK();
-        resid_mfma_kernel<Tx, false, Tb><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Yb, P.d_max, d + 1, T, P.n, flist, &st->nflag, 0,
+        resid_mfma_kernel<Tx, false, Tb><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Yb, ldb, d + 1, T, P.n, flist, &st->nflag, 0,
                                                     P.rc_rows, P.rc_S, rpart, P.n, nullptr);
         RBD_LAUNCH_CHECK();
         prof_end(RBD_PHASE_RESID, s);
@@ -579,8 +608,18 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     }
     return RBD_OK;
     };
+    // With an FP32 basis the first kY32Switch steps still run on the FP64 basis in Y
+    // (their passes are latency-bound: they gain nothing from fewer bytes), then the
+    // complete columns are rounded into the FP32 basis and the rest run on it.
+    const int dsw = Yf ? std::min(P.D, kY32Switch) : P.D;
     if (!W) {
-        const int rc = Yf ? identity_steps(Yf) : identity_steps(Y);
+        int rc = identity_steps(Y, 0, dsw);
+        if (rc == RBD_OK && Yf && P.D > dsw) {
+            const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(P.m * (kY32Switch - 8), 256));
+            y32_switch_kernel<<<g, 256, 0, s>>>(st, Y, P.d_max, Yf, P.ldyf, P.m, kY32Switch - 8);
+            RBD_LAUNCH_CHECK();
+            rc = identity_steps(Yf, dsw, P.D);
+        }
         if (rc != RBD_OK) return rc;
     }
     // diagonal A: two passes over Y per step (M = Y'WY kept up to date)
@@ -653,15 +692,18 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
         launch_ys_flush<true>(P, Y, st, 0, ys, s);
         RBD_LAUNCH_CHECK();
     } else {
-        // the last basis vector is still implicit: write it
-        if (Yf)
-            launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Yf, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], reinterpret_cast<const float*>(ys), s);
-        else
-            launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Y, st, 0, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
+        // the last basis vector is still implicit: write it (into the FP64 basis when the
+        // fit ended within its first dsw columns, else into the FP32 one)
+        launch_ycol_kc<true>(kc_for(std::max(dsw - 1, 0)), P, Y, st, dsw, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
         RBD_LAUNCH_CHECK();
+        if (Yf && P.D > dsw) {
+            launch_ycol_kc<true>(kc_for(std::max(P.D - 1, 0)), P, Yf, st, dsw, v1s[0], v1s[1], h2s[0], h2s[1], ys,
+                                 s);
+            RBD_LAUNCH_CHECK();
+        }
     }
     epilogue_kernel<<<eg, 256, 0, s>>>(st, e2, col_err, P.n, Y, P.m, P.d_max, T, pivots, err_hist, d_out, status,
-                                       stop_reason, Yf);
+                                       stop_reason, Yf, P.ldyf, dsw);
     RBD_LAUNCH_CHECK();
     prof_end(RBD_PHASE_EPILOGUE, s);
     return RBD_OK;

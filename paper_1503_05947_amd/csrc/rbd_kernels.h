@@ -1027,8 +1027,9 @@ __global__ __launch_bounds__(256) void tcorr2_kernel(const State* __restrict__ s
 // and copies the staged columns [8 floor(col / 8), col) from ys into Y, so
 // that Y(:, 0:col+1) is complete.
 // FINAL = false: col = d, before an exact refresh of this step (skipped when
-// none is queued).  FINAL = true: col = (final d) - 1, after the loop; the
-// buffers of that step are chosen by the parity of col.
+// none is queued).  FINAL = true: col = (final d) - 1, after the loop, written
+// only when col < d (rbd_fit_basis keeps later columns in FP32); the buffers
+// of that step are chosen by the parity of col.
 template <int KC, int RU, bool FINAL, bool NT, typename Tb = double>
 __global__ __launch_bounds__(256) void ycol_kernel(Tb* __restrict__ Y, int64_t ldy, int64_t m,
                                                     const State* __restrict__ st, int d, int rows_per_blk,
@@ -1036,10 +1037,10 @@ __global__ __launch_bounds__(256) void ycol_kernel(Tb* __restrict__ Y, int64_t l
                                                     const double* __restrict__ h2a, const double* __restrict__ h2b,
                                                     const Tb* __restrict__ ys) {
     int col;
-    if (FINAL) {
+    if (FINAL) {                 // d: only a final column below d is written here
         if (st->stop == kStopError) return;
         col = st->d - 1;
-        if (col < 0) return;
+        if (col < 0 || col >= d) return;
     } else {
         if (st->stop || st->nflag == 0) return;
         col = d;
@@ -1075,6 +1076,209 @@ __global__ __launch_bounds__(256) void ycol_kernel(Tb* __restrict__ Y, int64_t l
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// The same two passes with the basis kept in FP32 (rbd_fit_basis).  A lane
+// holds two adjacent columns (k = 2 lane + 128 c, c < KC2), read from Y with
+// one 8-byte load: FP32 values read one per lane halved the bytes each wave
+// keeps in flight and ran at 4.7 TB/s against 6.2.  The staged columns keep
+// the FP64 column-major slots of the FP64 pass (slot j of row r at
+// ys[j m + r], holding the FP32-rounded values): a step's store is then 64
+// contiguous bytes per row group (FP32 slots, stored 32 or 4 bytes at a time,
+// made every step 25-50 us slower), and the chunk that holds the staged block
+// reads a staged pair with two loads.  ldy is even.
+// ---------------------------------------------------------------------------
+// Entries (rb + u, k) and (rb + u, k + 1), k = 2 lane + 128 c, widened to
+// FP64; zero for rows >= r1 or columns >= cols.  Loads from clamped
+// addresses, all issued before the first widening.
+template <bool NT, int RU, int KC2>
+__device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const float* Y, int64_t ldy,
+                                              const double* ys, int64_t m, int64_t rb, int64_t r1, int lane,
+                                              int cols, int yb) {
+    const int cyb = yb / 128;                       // the chunk that holds the staged block (uniform)
+    f32x2 raw[RU][KC2];
+    double s0[RU], s1[RU];
+    const int ks = 2 * lane + 128 * cyb - yb;       // this lane's pair within the staged block
+    const bool in_st = ks >= 0 && ks < 8 && ks < cols - yb;     // at most four lanes read staged slots
+    const bool any_y = yb > 0;                      // uniform: some column is already in Y
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        const int64_t r = min(rb + u, r1 - 1);
+#pragma unroll
+        for (int c = 0; c < KC2; ++c) {
+            const int k = min(2 * lane + 128 * c, max(yb - 2, 0));
+            const f32x2* p = reinterpret_cast<const f32x2*>(Y + r * ldy + k);
+            if (any_y) raw[u][c] = NT ? __builtin_nontemporal_load(p) : *p;
+            else raw[u][c] = (f32x2){0.f, 0.f};
+        }
+        s0[u] = in_st ? ys[ks * m + r] : 0.0;               // FP64: no widening under the test
+        s1[u] = in_st ? ys[(ks + 1) * m + r] : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);              // every load above issues before the first use below
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int c = 0; c < KC2; ++c) {
+            const int k = 2 * lane + 128 * c;
+            const bool ok = rb + u < r1;
+            const bool st = k >= yb;                    // a staged pair (it lies in chunk cyb)
+            const double a = st ? s0[u] : (double)raw[u][c].x, b = st ? s1[u] : (double)raw[u][c].y;
+            y[u][c][0] = (ok && k < cols) ? a : 0.0;
+            y[u][c][1] = (ok && k + 1 < cols) ? b : 0.0;
+        }
+}
+
+// cgs1_lag for an FP32 basis: the arithmetic of cgs1_lag_kernel, the deferred
+// column rounded to FP32 as it is stored (every pass uses the stored value).
+template <int KC2, int RU, bool NT>
+__global__ __launch_bounds__(256) void cgs1_lag32_kernel(const double* __restrict__ xp, int64_t m,
+                                                          float* __restrict__ Y, int64_t ldy,
+                                                          const double* __restrict__ T, int64_t ldt,
+                                                          State* __restrict__ st, int d, int rows_per_blk,
+                                                          const double* __restrict__ v1p,
+                                                          const double* __restrict__ h2p, double* __restrict__ v1,
+                                                          double* __restrict__ ys, double* __restrict__ part,
+                                                          int64_t ldp) {
+    static_assert(RU <= kWave / 8, "eight lanes per row in flight for the block write");
+    if (st->stop) return;
+    constexpr int KW = 128 * KC2;
+    __shared__ double hs[KW];
+    __shared__ double gs[KW];
+    __shared__ double accs[KW];
+    __shared__ double sred[4];
+    const int p = st->p;
+    const double invp = st->inv_nu;
+    const int dl = d - 1;                          // the deferred column (none at d = 0)
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) {
+        hs[k] = (k < d) ? T[(int64_t)k * ldt + p] : 0.0;
+        gs[k] = (k < dl) ? h2p[k] : 0.0;
+        accs[k] = 0.0;
+    }
+    __syncthreads();
+    const double hl = dl >= 0 ? hs[dl] : 0.0;
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int cl = dl >= 0 ? dl / 128 : -1, ll = dl >= 0 ? (dl % 128) / 2 : -1, hlf = dl >= 0 ? dl % 2 : 0;
+    const int yb = dl >= 0 ? (dl & ~7) : 0;
+    const bool blk = dl >= 0 && (dl & 7) == 7;
+    const int ju = lane >> 3, jj = lane & 7;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    double acc[KC2][2];
+#pragma unroll
+    for (int c = 0; c < KC2; ++c) acc[c][0] = acc[c][1] = 0.0;
+    double nacc = 0.0;
+    for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
+        const int64_t rl = rb + lane;
+        const bool okl = lane < RU && rl < r1;
+        const double xl = okl ? xp[rl] : 0.0;
+        const double vl = (okl && dl >= 0) ? v1p[rl] : 0.0;
+        const bool okb = blk && ju < RU && rb + ju < r1;
+        const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
+        double y[RU][KC2][2];
+        double dots[2 * RU];
+        load_y32_rows<NT, RU, KC2>(y, Y, ldy, ys, m, rb, r1, lane, dl, yb);
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int k = 2 * lane + 128 * c + h;
+                    a = fma(y[u][c][h], gs[k], a);
+                    b = fma(y[u][c][h], hs[k], b);
+                }
+            dots[u] = a;
+            dots[RU + u] = b;
+        }
+        wave_sum_n<2 * RU>(dots);
+        double vo = 0.0, yo = 0.0, yb7 = 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const double yl = dl >= 0 ? (double)(float)((lane_bcast(vl, u) - dots[u]) * invp) : 0.0;
+            const double v = lane_bcast(xl, u) - dots[RU + u] - yl * hl;
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    if (c == cl && lane == ll && h == hlf) y[u][c][h] = yl;
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[c][h] = fma(y[u][c][h], v, acc[c][h]);
+            if (lane == u) { vo = v; yo = yl; }
+            if (ju == u) yb7 = yl;
+        }
+        if (okl) {
+            v1[rl] = vo;
+            nacc = fma(vo, vo, nacc);
+            if (dl >= 0) ys[(int64_t)(dl - yb) * m + rl] = yo;
+        }
+        if (okb) Y[(rb + ju) * ldy + yb + jj] = (float)(jj < 7 ? sv : yb7);
+    }
+    const double nn = block_sum(nacc, sred);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
+    if (d == 0) return;
+    for (int q = 0; q < nw; ++q) {
+        if (w == q) {
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) accs[2 * lane + 128 * c + h] += acc[c][h];
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < d; k += blockDim.x) part[(int64_t)blockIdx.x * ldp + k] = accs[k];
+}
+
+// ycol for an FP32 basis (see ycol_kernel): the deferred column into Y and
+// the staged columns [8 floor(col / 8), col) from their slots.
+template <int KC2, int RU, bool FINAL, bool NT>
+__global__ __launch_bounds__(256) void ycol32_kernel(float* __restrict__ Y, int64_t ldy, int64_t m,
+                                                      const State* __restrict__ st, int d, int rows_per_blk,
+                                                      const double* __restrict__ v1a, const double* __restrict__ v1b,
+                                                      const double* __restrict__ h2a, const double* __restrict__ h2b,
+                                                      const double* __restrict__ ys) {
+    int col;
+    if (FINAL) {                 // d: only a final column at or above d is written here
+        if (st->stop == kStopError) return;
+        col = st->d - 1;
+        if (col < 0 || col < d) return;
+    } else {
+        if (st->stop || st->nflag == 0) return;
+        col = d;
+    }
+    const double* v1 = (col & 1) ? v1b : v1a;
+    const double* h2 = (col & 1) ? h2b : h2a;
+    constexpr int KW = 128 * KC2;
+    __shared__ double hs[KW];
+    for (int k = threadIdx.x; k < KW; k += blockDim.x) hs[k] = (k < col) ? h2[k] : 0.0;
+    __syncthreads();
+    const double inv = st->inv_nu;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int yb = col & ~7;
+    const int ju = lane >> 3, jj = lane & 7;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+    const int64_t r1 = min(m, r0 + (int64_t)rows_per_blk);
+    for (int64_t rb = r0 + (int64_t)wv * RU; rb < r1; rb += (int64_t)nw * RU) {
+        double y[RU][KC2][2];
+        load_y32_rows<NT, RU, KC2>(y, Y, ldy, ys, m, rb, r1, lane, col, yb);
+        double dot[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            dot[u] = 0.0;
+#pragma unroll
+            for (int c = 0; c < KC2; ++c)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) dot[u] = fma(y[u][c][h], hs[2 * lane + 128 * c + h], dot[u]);
+        }
+        wave_sum_n<RU>(dot);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (lane == u && rb + u < r1) Y[(rb + u) * ldy + col] = (float)((v1[rb + u] - dot[u]) * inv);
+        if (ju < RU && rb + ju < r1 && yb + jj < col) Y[(rb + ju) * ldy + yb + jj] = (float)ys[(int64_t)jj * m + rb + ju];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // reduce_rows: out[g * ldo + c] = sum over rows r of group g (rows g*per ..
@@ -1496,23 +1700,47 @@ __global__ __launch_bounds__(256) void read_stream_kernel(const u32x4* __restric
 }
 
 // ---------------------------------------------------------------------------
+// y32_switch: rbd_fit_basis runs its first steps on the FP64 basis in Y and,
+// once the fit passes that many columns, rounds the complete columns
+// [0, ncols) into the FP32 basis (the rest of the open block is staged and
+// reaches the FP32 basis through the next pass).  Nothing when the fit has
+// stopped.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void y32_switch_kernel(const State* __restrict__ st, const double* __restrict__ Y,
+                                                          int64_t ldy, float* __restrict__ Yf, int64_t ldyf,
+                                                          int64_t m, int ncols) {
+    if (st->stop) return;
+    const int64_t tot = m * (int64_t)ncols;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += stride) {
+        const int64_t i = e / ncols, k = e % ncols;
+        Yf[i * ldyf + k] = (float)Y[i * ldy + k];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // epilogue: col_err = sqrt(e^2), zero unused columns/rows, publish d and status.
 // ---------------------------------------------------------------------------
 __global__ void epilogue_kernel(const State* __restrict__ st, const double* __restrict__ e2,
                                 double* __restrict__ col_err, int64_t n, double* __restrict__ Y, int64_t m,
                                 int d_max, double* __restrict__ T, int64_t* __restrict__ pivots,
                                 double* __restrict__ err_hist, int32_t* d_out, int32_t* status,
-                                int32_t* stop_reason, const float* __restrict__ Yf = nullptr) {
+                                int32_t* stop_reason, const float* __restrict__ Yf = nullptr, int64_t ldyf = 0,
+                                int ysw = 0) {
     const int d = st->d;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = gid; j < n; j += stride) col_err[j] = sqrt(e2[j]);
-    if (Yf) {                 // an FP32 basis: the output is its FP64 copy, zero beyond column d
+    const bool from_f = Yf && d > ysw;   // the FP32 basis was in use (the fit passed column ysw)
+    if (from_f) {             // the output is its FP64 copy, zero beyond column d
         const int64_t tot = m * (int64_t)d_max;
-        for (int64_t e = gid; e < tot; e += stride) Y[e] = (e % d_max) < d ? (double)Yf[e] : 0.0;
+        for (int64_t e = gid; e < tot; e += stride) {
+            const int64_t i = e / d_max, k = e % d_max;
+            Y[e] = k < d ? (double)Yf[i * ldyf + k] : 0.0;
+        }
     }
     if (d < d_max) {
-        if (!Yf)
+        if (!from_f)
             for (int64_t i = gid; i < m; i += stride)
                 for (int k = d; k < d_max; ++k) Y[i * d_max + k] = 0.0;
         const int64_t tot = (int64_t)(d_max - d) * n;

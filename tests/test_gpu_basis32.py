@@ -1,12 +1,16 @@
-"""rbd_fit_basis with the basis kept in FP32 while the loop runs (meant for
-BF16-stored data) against the FP64 oracle.
+"""rbd_fit_basis with the basis kept in FP32 once the fit passes 128 columns
+(meant for BF16-stored data) against the FP64 oracle, and against rbd_fit for
+fits that end within 128 columns (those run rbd_fit's steps exactly).  The
+test inputs are small, so they run with RBD_LOOP=0: inputs of at most 64 MB
+otherwise take the single-launch loop, which keeps the FP64 basis.
 
-The stored basis is the FP64 one rounded to FP32 (orthonormal to about 1e-7),
-and the downdated errors carry an absolute error of order
-2^-24 ||x_j||^2 / e_j between exact refreshes; the checks use that accuracy:
-basis vectors orthonormal to 1e-6, errors to max(1e-5, 2^-22 E_0 / E_d) E_0,
-pivots compared where the oracle's top two errors differ by more than 1e-5 E_0.
-Every case prints its name before touching the GPU."""
+Past 128 columns the stored basis is the FP64 one rounded to FP32
+(orthonormal to about 1e-7), and the downdated errors carry an absolute error
+of order 2^-24 ||x_j||^2 / e_j between exact refreshes; the checks use that
+accuracy: basis vectors orthonormal to 1e-6, errors to
+max(1e-5, 2^-22 E_0 / E_d) E_0, pivots compared where the oracle's top two
+errors differ by more than 1e-5 E_0.  Every case prints its name before
+touching the GPU."""
 import numpy as np
 import pytest
 
@@ -16,6 +20,12 @@ from parity import compare_fit
 from test_gpu_fit import to_device
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def per_kernel_driver(monkeypatch, request):
+    if "loop" not in request.fixturenames:
+        monkeypatch.setenv("RBD_LOOP", "0")
 
 
 def run(stored, dtype, tol, d_max, rel=False, basis="f32"):
@@ -37,31 +47,76 @@ def check32(name, stored, vals, dtype, tol, d_max, rel=False, exact_d=True):
     return dev, ref
 
 
-@pytest.mark.parametrize("dtype", ["bf16", "f32"])
-def test_lowrank(dtype):
-    w = synth.lowrank_spectrum(2)
-    stored, vals = synth.quantize(w.X, dtype)
-    dev, ref = check32("lowrank rel 1e-2", stored, vals, dtype, 1e-2, 64, rel=True)
-    assert dev["stop"] == "tol"
-
-
-def test_bump_field_bf16():
+def test_bump_field_bf16_256_steps():
     w = synth.bump_field(0)
     stored, vals = synth.quantize(w.X, "bf16")
-    check32("bump 2048^2 rel 1e-3", stored, vals, "bf16", 1e-3, 256, rel=True)
+    dev, _ = check32("bump 2048^2 fixed 256", stored, vals, "bf16", 0.0, 256, exact_d=False)
+    assert dev["d"] == 256
 
 
-def test_ragged_fixed_steps_to_the_bf16_floor():
-    w = synth.bump_field(2, m=1111, n=777)
+def test_ragged_fixed_steps_past_the_switch():
+    w = synth.bump_field(2, m=1111, n=777, noise=1e-2)
     stored, vals = synth.quantize(w.X, "bf16")
-    dev, ref = check32("ragged 1111x777 fixed 60", stored, vals, "bf16", 0.0, 60, exact_d=False)
-    assert dev["d"] == 60
+    dev, _ = check32("ragged 1111x777 fixed 200", stored, vals, "bf16", 0.0, 200, exact_d=False)
+    assert dev["d"] == 200
 
 
-def test_parametric_small_grid_bf16():
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_parametric_small_grid_past_the_switch(dtype):
     pf = synth.parametric_field(0, grid=48, n=300)
-    stored, vals = synth.quantize(pf.full(), "bf16")
-    check32("parametric 48^2 fixed 40", stored, vals, "bf16", 0.0, 40, exact_d=False)
+    stored, vals = synth.quantize(pf.full(), dtype)
+    dev, _ = check32("parametric 48^2 fixed 160", stored, vals, dtype, 0.0, 160, exact_d=False)
+    assert dev["d"] == 160
+
+
+@pytest.mark.parametrize("d_max", [128, 129, 136])
+def test_switch_boundaries(d_max):
+    """Fits that end exactly at, one past and one block past the switch column."""
+    w = synth.bump_field(5, m=900, n=700, noise=1e-2)
+    stored, vals = synth.quantize(w.X, "bf16")
+    dev, _ = check32(f"bump 900x700 fixed {d_max}", stored, vals, "bf16", 0.0, d_max, exact_d=False)
+    assert dev["d"] == d_max
+
+
+@pytest.mark.parametrize("loop", ["0", "auto"])
+@pytest.mark.parametrize("case", ["lowrank", "bump_rel_1e-2", "bump_128"])
+def test_within_128_columns_equals_rbd_fit(case, loop, monkeypatch):
+    """A fit that ends within 128 columns runs rbd_fit's steps (and an input the
+    single-launch loop takes runs rbd_fit itself): identical results."""
+    import paper_1503_05947_amd as rbd
+    if loop == "0":
+        monkeypatch.setenv("RBD_LOOP", "0")
+    else:
+        monkeypatch.delenv("RBD_LOOP", raising=False)
+    if case == "lowrank":
+        stored, _ = synth.quantize(synth.lowrank_spectrum(2).X, "bf16")
+        tol, rel, d_max = 1e-2, True, 64
+    elif case == "bump_rel_1e-2":
+        stored, _ = synth.quantize(synth.bump_field(0).X, "bf16")
+        tol, rel, d_max = 1e-2, True, 512
+    else:
+        stored, _ = synth.quantize(synth.bump_field(3, m=1500, n=1300).X, "bf16")
+        tol, rel, d_max = 0.0, False, 128
+    print(f"[gpu] basis f32 = f64 within 128 columns: {case}, RBD_LOOP={loop}", flush=True)
+    X = to_device(stored, "bf16")
+    a = rbd.fit(X, tol=tol, d_max=d_max, rel=rel, basis="f64")
+    b = rbd.fit(X, tol=tol, d_max=d_max, rel=rel, basis="f32")
+    assert a.d <= 128 and a.d == b.d
+    for k in ("Y", "T", "pivots", "col_err", "err_hist"):
+        assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
+
+
+def test_small_input_past_128_columns_keeps_the_loop(monkeypatch):
+    """Inputs the single-launch loop takes keep the FP64 basis in every mode."""
+    import paper_1503_05947_amd as rbd
+    monkeypatch.delenv("RBD_LOOP", raising=False)
+    stored, _ = synth.quantize(synth.bump_field(6, m=1200, n=900, noise=1e-2).X, "bf16")
+    print("[gpu] basis f32 on a cache-resident input, 200 steps", flush=True)
+    X = to_device(stored, "bf16")
+    a = rbd.fit(X, tol=0.0, d_max=200, basis="f64")
+    b = rbd.fit(X, tol=0.0, d_max=200, basis="f32")
+    for k in ("Y", "T", "pivots", "col_err", "err_hist"):
+        assert np.array_equal(getattr(a, k).cpu().numpy(), getattr(b, k).cpu().numpy()), k
 
 
 def test_f64_basis_entry_point_equals_rbd_fit():
