@@ -615,8 +615,8 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     if (!W) {
         int rc = identity_steps(Y, 0, dsw);
         if (rc == RBD_OK && Yf && P.D > dsw) {
-            const unsigned g = (unsigned)std::min<int64_t>(8192, cdiv(P.m * (kY32Switch - 8), 256));
-            y32_switch_kernel<<<g, 256, 0, s>>>(st, Y, P.d_max, Yf, P.ldyf, P.m, kY32Switch - 8);
+            static_assert(kY32Switch - 8 <= 128, "y32_switch_kernel copies at most 128 columns per row");
+            y32_switch_kernel<<<(unsigned)cdiv(P.m, 2), 256, 0, s>>>(st, Y, P.d_max, Yf, P.ldyf, P.m, kY32Switch - 8);
             RBD_LAUNCH_CHECK();
             rc = identity_steps(Yf, dsw, P.D);
         }

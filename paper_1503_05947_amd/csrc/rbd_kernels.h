@@ -1100,7 +1100,6 @@ __device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const flo
     double s0[RU], s1[RU];
     const int ks = 2 * lane + 128 * cyb - yb;       // this lane's pair within the staged block
     const bool in_st = ks >= 0 && ks < 8 && ks < cols - yb;     // at most four lanes read staged slots
-    const bool any_y = yb > 0;                      // uniform: some column is already in Y
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
         const int64_t r = min(rb + u, r1 - 1);
@@ -1108,8 +1107,7 @@ __device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const flo
         for (int c = 0; c < KC2; ++c) {
             const int k = min(2 * lane + 128 * c, max(yb - 2, 0));
             const f32x2* p = reinterpret_cast<const f32x2*>(Y + r * ldy + k);
-            if (any_y) raw[u][c] = NT ? __builtin_nontemporal_load(p) : *p;
-            else raw[u][c] = (f32x2){0.f, 0.f};
+            raw[u][c] = NT ? __builtin_nontemporal_load(p) : *p;
         }
         s0[u] = in_st ? ys[ks * m + r] : 0.0;               // FP64: no widening under the test
         s1[u] = in_st ? ys[(ks + 1) * m + r] : 0.0;
@@ -1706,16 +1704,14 @@ __global__ __launch_bounds__(256) void read_stream_kernel(const u32x4* __restric
 // reaches the FP32 basis through the next pass).  Nothing when the fit has
 // stopped.
 // ---------------------------------------------------------------------------
+// Two rows per workgroup of 256 threads, one column per thread (ncols <= 128).
 __global__ __launch_bounds__(256) void y32_switch_kernel(const State* __restrict__ st, const double* __restrict__ Y,
                                                           int64_t ldy, float* __restrict__ Yf, int64_t ldyf,
                                                           int64_t m, int ncols) {
     if (st->stop) return;
-    const int64_t tot = m * (int64_t)ncols;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += stride) {
-        const int64_t i = e / ncols, k = e % ncols;
-        Yf[i * ldyf + k] = (float)Y[i * ldy + k];
-    }
+    const int64_t i = 2 * (int64_t)blockIdx.x + threadIdx.x / 128;
+    const int k = threadIdx.x % 128;
+    if (i < m && k < ncols) Yf[i * ldyf + k] = (float)Y[i * ldy + k];
 }
 
 // ---------------------------------------------------------------------------
