@@ -40,12 +40,29 @@ hipError_t gemm(int64_t M, int64_t N, int64_t K, double alpha, const TAe* A, int
 // rank[k] = the rank of pivot k (ties, which distinct pivots never have, are
 // broken by position, so ranks are distinct).  One thread per column and per
 // pivot, the pivots staged in LDS.
+// With Rp, the same launch also gathers R's upper triangle packed by columns
+// (column i holds R(0..i, i) at i (i + 1) / 2) and the reciprocals of its
+// diagonal after it, once, for the inverse below.
 __global__ __launch_bounds__(256) void pivot_rank_kernel(const int64_t* __restrict__ piv, int d, int64_t n,
-                                                         int* __restrict__ colrank, int* __restrict__ rank) {
+                                                         int* __restrict__ colrank, int* __restrict__ rank,
+                                                         const double* __restrict__ T, int64_t ldt,
+                                                         double* __restrict__ Rp) {
     __shared__ int64_t ps[RBD_MAX_D];
     for (int k = threadIdx.x; k < d; k += blockDim.x) ps[k] = piv[k];
     __syncthreads();
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (Rp) {
+        const int64_t tri = (int64_t)d * (d + 1) / 2;
+        for (int64_t e = j; e < tri; e += (int64_t)gridDim.x * blockDim.x) {
+            int64_t i = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);      // column: i (i + 1) / 2 <= e
+            while (i * (i + 1) / 2 > e) --i;
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            const int64_t k = e - i * (i + 1) / 2;
+            const double v = T[k * ldt + ps[i]];
+            Rp[e] = v;
+            if (k == i) Rp[tri + i] = 1.0 / v;
+        }
+    }
     if (j <= n) {
         int lb = 0;
         bool hit = false;
@@ -86,37 +103,15 @@ __global__ void rinv_kernel(const double* __restrict__ T, int64_t ldt, const int
 // and l + 64 of b (then x) in registers; a step is one lane broadcast and one
 // multiply-add per row, with no cross-lane sum.  R's upper triangle is staged
 // in LDS once per workgroup, packed by columns (column i holds rows 0..i at
-// i (i + 1) / 2), with the reciprocals of its diagonal after it; the staging
-// loads go out in groups of 32 from clamped addresses (a load under the
-// triangle test would wait for its data before the next one issues).
+// i (i + 1) / 2), with the reciprocals of its diagonal after it, copied from
+// the packed form pivot_rank_kernel gathered once.
 constexpr int kRinvLds = 128;
-__global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict__ T, int64_t ldt,
-                                                       const int64_t* __restrict__ piv, int d,
+__global__ __launch_bounds__(256) void rinv_lds_kernel(const double* __restrict__ Rp, int d,
                                                        const int* __restrict__ rank, double* __restrict__ Rinv) {
     extern __shared__ double Rc[];           // packed R by columns: d (d + 1) / 2, then 1 / R(i, i): d
-    __shared__ int64_t ps[kRinvLds];
     double* rd = Rc + d * (d + 1) / 2;
-    for (int k = threadIdx.x; k < d; k += blockDim.x) ps[k] = piv[k];
-    __syncthreads();
-    constexpr int U = 32;
-    for (int e0 = threadIdx.x; e0 < d * d; e0 += U * blockDim.x) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = min(e0 + u * (int)blockDim.x, d * d - 1);
-            const int k = e / d, i = e % d;
-            v[u] = T[(int64_t)min(k, i) * ldt + ps[i]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * (int)blockDim.x;
-            const int k = e / d, i = e % d;
-            if (e < d * d && k <= i) {
-                Rc[i * (i + 1) / 2 + k] = v[u];
-                if (k == i) rd[i] = 1.0 / v[u];
-            }
-        }
-    }
+    const int tot = d * (d + 1) / 2 + d;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) Rc[e] = Rp[e];     // contiguous, all in flight
     __syncthreads();
     const int lane = threadIdx.x % kWave;
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -147,7 +142,7 @@ __global__ void copyltu_kernel(const double* __restrict__ Mm, int d, double* __r
 }
 
 struct BwdPlan {
-    size_t o_c1, o_ybar, o_m, o_s, o_rinv, o_abar, o_colrank, o_rank, o_part, total;
+    size_t o_c1, o_ybar, o_m, o_s, o_rinv, o_abar, o_colrank, o_rank, o_rp, o_part, total;
 };
 
 bool make_bwd_plan(int64_t m, int64_t n, int32_t d, BwdPlan* P) {
@@ -166,6 +161,7 @@ bool make_bwd_plan(int64_t m, int64_t n, int32_t d, BwdPlan* P) {
     P->o_abar = take(8 * (size_t)m * d);
     P->o_colrank = take(4 * ((size_t)n + 1));
     P->o_rank = take(4 * (size_t)d);
+    P->o_rp = take(8 * ((size_t)d * (d + 1) / 2 + d));
     P->o_part = take(8 * kPartElems);
     P->total = o;
     return true;
@@ -184,6 +180,7 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     double* part = reinterpret_cast<double*>(ws + P.o_part);
     int* colrank = reinterpret_cast<int*>(ws + P.o_colrank);
     int* rank = reinterpret_cast<int*>(ws + P.o_rank);
+    double* Rp = reinterpret_cast<double*>(ws + P.o_rp);
     hipError_t e = hipSuccess;
     auto ok = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     // C1 = Y'G (d x n)
@@ -196,18 +193,21 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     copyltu_kernel<<<(unsigned)cd((int64_t)d * d, 256), 256, 0, s>>>(Mm, d, S);
     ok(hipGetLastError());
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
-    // Abar' = Ybar R^{-T} with its columns in pivot-rank order
-    pivot_rank_kernel<<<(unsigned)cd(std::max<int64_t>(n + 1, d), 256), 256, 0, s>>>(piv, d, n, colrank, rank);
+    // Rinv' = R^{-1}, rows in pivot-rank order (R gathered once by pivot_rank_kernel when d <= kRinvLds)
+    const bool lds_inv = d <= kRinvLds;
+    pivot_rank_kernel<<<(unsigned)cd(std::max<int64_t>(n + 1, d), 256), 256, 0, s>>>(piv, d, n, colrank, rank, T,
+                                                                                     ldt, lds_inv ? Rp : nullptr);
     ok(hipGetLastError());
-    if (d <= kRinvLds) {
+    if (lds_inv) {
         const size_t lds = sizeof(double) * ((size_t)d * (d + 1) / 2 + d);
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&rinv_lds_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(T, ldt, piv, d, rank, Rinv);
+        rinv_lds_kernel<<<(unsigned)cd(d, 4), 256, lds, s>>>(Rp, d, rank, Rinv);
     } else {
         rinv_kernel<<<(unsigned)cd(d, 64), 64, 0, s>>>(T, ldt, piv, d, rank, Rinv);
     }
     ok(hipGetLastError());
+    // Abar' = Ybar R^{-T} with its columns in pivot-rank order
     ok(gemm<false, true, double, double>(m, d, d, 1.0, Ybar, d, Rinv, d, 0.0, Abar, d, nullptr, 0, s));
     // dX = Y C1 + scatter_P(Abar): each tile of dX adds the Abar' columns of the pivots among its
     // columns as extra k-steps of its own product (dX is written once)
