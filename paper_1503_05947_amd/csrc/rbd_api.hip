@@ -552,61 +552,61 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
     // the basis is kept in Y itself, or in FP32 in the workspace (copied out by the epilogue)
     float* const Yf = P.y32 ? reinterpret_cast<float*>(ws + P.o_yf) : nullptr;
     auto identity_steps = [&](auto* Yb, int d0, int d1) -> int {
-    using Tb = std::remove_pointer_t<decltype(Yb)>;
-    const int64_t ldb = std::is_same<Tb, float>::value ? P.ldyf : P.d_max;
-    for (int d = d0; d < d1; ++d) {
-        const int c = d & 1;
-        const int kc = kc_for(d);
-        prof_begin(RBD_PHASE_CGS1, s);
-        launch_gather<Tx>(P, X, ldx, st, xp, s);
-        RBD_LAUNCH_CHECK();
-        switch (kc) {
-            case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-            default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+        using Tb = std::remove_pointer_t<decltype(Yb)>;
+        const int64_t ldb = std::is_same<Tb, float>::value ? P.ldyf : P.d_max;
+        for (int d = d0; d < d1; ++d) {
+            const int c = d & 1;
+            const int kc = kc_for(d);
+            prof_begin(RBD_PHASE_CGS1, s);
+            launch_gather<Tx>(P, X, ldx, st, xp, s);
+            RBD_LAUNCH_CHECK();
+            switch (kc) {
+                case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+            }
+            RBD_LAUNCH_CHECK();
+            launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_CGS1, s);
+            prof_begin(RBD_PHASE_CGS2, s);
+            const int kp = d > 0 ? (int)cdiv(d, kTcorr) : 0;
+            nu_tcorr_kernel<<<dim3(kp ? (unsigned)cdiv(P.n, 256) : 1u, (unsigned)std::max(kp, 1)), 256, 0, s>>>(
+                st, h2s[c], d, T, P.n, P.n, part + (int64_t)P.sc_S * P.n);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_CGS2, s);
+            prof_begin(RBD_PHASE_XSCAN, s);
+            launch_xscan<Tx, kScanDot>(P, X, ldx, v1s[c], st, Y, -1, part, vec_ok, nt, s);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_XSCAN, s);
+            prof_begin(RBD_PHASE_UPDATE, s);
+            const int rows = P.sc_S + kp;
+            const int groups = (int)cdiv(rows, up_per);
+            reduce_rows_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)groups), 256, 0, s>>>(st, part, P.n, rows,
+                                                                                               up_per, P.n, l2, P.n);
+            RBD_LAUNCH_CHECK();
+            update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n,
+                                                          flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_UPDATE, s);
+            prof_begin(RBD_PHASE_RESID, s);
+            // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
+            launch_ycol_kc<false>(kc, P, Yb, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
+            RBD_LAUNCH_CHECK();
+            resid_mfma_kernel<Tx, false, Tb><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Yb, ldb, d + 1, T, P.n, flist, &st->nflag, 0,
+                                                        P.rc_rows, P.rc_S, rpart, P.n, nullptr);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_RESID, s);
+            prof_begin(RBD_PHASE_RESID_FINISH, s);
+            resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, rpart, P.n, P.rc_S, flist, e2, base2, P.n, tickets, pivots,
+                                                          err_hist, d);
+            RBD_LAUNCH_CHECK();
+            prof_end(RBD_PHASE_RESID_FINISH, s);
+            prof_step(s);
         }
-        RBD_LAUNCH_CHECK();
-        launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_CGS1, s);
-        prof_begin(RBD_PHASE_CGS2, s);
-        const int kp = d > 0 ? (int)cdiv(d, kTcorr) : 0;
-        nu_tcorr_kernel<<<dim3(kp ? (unsigned)cdiv(P.n, 256) : 1u, (unsigned)std::max(kp, 1)), 256, 0, s>>>(
-            st, h2s[c], d, T, P.n, P.n, part + (int64_t)P.sc_S * P.n);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_CGS2, s);
-        prof_begin(RBD_PHASE_XSCAN, s);
-        launch_xscan<Tx, kScanDot>(P, X, ldx, v1s[c], st, Y, -1, part, vec_ok, nt, s);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_XSCAN, s);
-        prof_begin(RBD_PHASE_UPDATE, s);
-        const int rows = P.sc_S + kp;
-        const int groups = (int)cdiv(rows, up_per);
-        reduce_rows_kernel<<<dim3((unsigned)cdiv(P.n, 256), (unsigned)groups), 256, 0, s>>>(st, part, P.n, rows,
-                                                                                           up_per, P.n, l2, P.n);
-        RBD_LAUNCH_CHECK();
-        update_kernel<kStep><<<P.up_ncb, 256, 0, s>>>(P.n, st, d, l2, groups, tickets, e2, base2, T, P.n,
-                                                      flist, bres_v, bres_i, pivots, err_hist, start, tol, rel);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_UPDATE, s);
-        prof_begin(RBD_PHASE_RESID, s);
-        // an exact refresh of this step needs Y(:, d): write it now (skipped when nothing is queued)
-        launch_ycol_kc<false>(kc, P, Yb, st, d, v1s[0], v1s[1], h2s[0], h2s[1], ys, s);
-        RBD_LAUNCH_CHECK();
-        resid_mfma_kernel<Tx, false, Tb><<<P.rc_grid, 256, 0, s>>>(X, ldx, P.m, Yb, ldb, d + 1, T, P.n, flist, &st->nflag, 0,
-                                                    P.rc_rows, P.rc_S, rpart, P.n, nullptr);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_RESID, s);
-        prof_begin(RBD_PHASE_RESID_FINISH, s);
-        resid_finish_kernel<<<P.rf_grid, 256, 0, s>>>(st, rpart, P.n, P.rc_S, flist, e2, base2, P.n, tickets, pivots,
-                                                      err_hist, d);
-        RBD_LAUNCH_CHECK();
-        prof_end(RBD_PHASE_RESID_FINISH, s);
-        prof_step(s);
-    }
-    return RBD_OK;
+        return RBD_OK;
     };
     // With an FP32 basis the first kY32Switch steps still run on the FP64 basis in Y
     // (their passes are latency-bound: they gain nothing from fewer bytes), then the
