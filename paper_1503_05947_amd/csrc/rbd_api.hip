@@ -712,9 +712,10 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
 // ---------------------------------------------------------------------------
 // General SPD A (section 3.2) in CSR form.  Same loop as the diagonal case,
 // with A xi from a sparse product.  Exact refreshes need the residual columns
-// themselves (r' A r), so they run in chunks whose number depends on how many
-// columns are queued: the host reads the loop state after each step's update
-// (one stream synchronisation per step) and launches exactly those chunks.
+// themselves (r' A r), so they run in chunks of queued columns: every step
+// enqueues the chunks for the longest possible queue, and each chunk reads the
+// queue's length on the device and exits at once when it has nothing to do,
+// so the host never waits on the stream.
 // ---------------------------------------------------------------------------
 struct SpdPlan {
     FitPlan F;

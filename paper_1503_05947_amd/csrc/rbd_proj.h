@@ -68,11 +68,17 @@ template <> struct Raw4<f16_t> : Raw4Half<f16_t> {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int kProjCols = 256;      // columns per workgroup
-// k-steps of operands held in registers: the budget of two waves per SIMD
-// (measured on MI355X: one wave per SIMD left the matrix cores idle most of
-// the time) ...
+// Waves per SIMD: three where the accumulators leave room (up to 32 rows of C,
+// or 48 for FP32 queries: 6.35 -> 5.2-5.3 ms for a batch of 262,144 FP32
+// queries of 10,304 entries against two per SIMD), two otherwise (one wave per SIMD left the
+// matrix cores idle most of the time) ...
+template <typename Tv, int MT> constexpr int proj_occupancy() {
+    return (MT <= 2 || (sizeof(Tv) == 4 && MT == 3)) ? 3 : 2;
+}
+// ... and the k-steps of operands held in registers within that budget ...
 template <typename Tv, int MT> constexpr int proj_regs() {
-    return (sizeof(Tv) == 8 && MT == 4) ? 2 : ((sizeof(Tv) == 8 || MT == 4) ? 4 : 8);
+    return proj_occupancy<Tv, MT>() == 3 ? 4
+                                          : ((sizeof(Tv) == 8 && MT == 4) ? 2 : ((sizeof(Tv) == 8 || MT == 4) ? 4 : 8));
 }
 // ... held as B buffers of G k-steps (B * G = proj_regs): while one buffer is
 // multiplied, B - 1 are in flight
@@ -81,7 +87,7 @@ template <typename Tv, int MT> constexpr int proj_bufs() { return proj_regs<Tv, 
 constexpr int kProjStepMax = 16;    // row chunks of a k-split are a multiple of this
 
 template <typename Tv, int MT>
-__global__ __launch_bounds__(256) void proj_mfma_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m, int d,
+__global__ __launch_bounds__(256, (proj_occupancy<Tv, MT>())) void proj_mfma_kernel(const double* __restrict__ Y, int64_t ldy, int64_t m, int d,
                                                          const Tv* __restrict__ V, int64_t ldv, int64_t N,
                                                          int64_t kchunk, int vec_ok, double* __restrict__ C,
                                                          int64_t ldc, double* __restrict__ part) {
