@@ -894,6 +894,10 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
     double acc[KC];
 #pragma unroll
     for (int c = 0; c < KC; ++c) acc[c] = 0.0;
+    // the deferred column's products, kept apart (its loaded entries are zero;
+    // chunk cl is uniform) and added into acc[cl] at the end: the same sums
+    // as forming them in place, without a select per entry
+    double accl = 0.0;
     double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
         // lane u < RU carries row rb + u's scalars (one load / store instruction per group)
@@ -925,10 +929,8 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
             const double yl = dl >= 0 ? (double)(Tb)((lane_bcast(vl, u) - dots[u]) * invp) : 0.0;
             const double v = lane_bcast(xl, u) - dots[RU + u] - yl * hl;
 #pragma unroll
-            for (int c = 0; c < KC; ++c)
-                if (c == cl && lane == ll) y[u][c] = yl;
-#pragma unroll
             for (int c = 0; c < KC; ++c) acc[c] = fma(y[u][c], v, acc[c]);
+            accl = fma(lane == ll ? yl : 0.0, v, accl);
             if (lane == u) { vo = v; yo = yl; }
             if (ju == u) yb7 = yl;
         }
@@ -939,6 +941,9 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         }
         if (okb) Y[(rb + ju) * ldy + yb + jj] = jj < 7 ? sv : (Tb)yb7;
     }
+#pragma unroll
+    for (int c = 0; c < KC; ++c)
+        if (c == cl) acc[c] += accl;
     const double nn = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
     if (d == 0) return;
@@ -1164,6 +1169,7 @@ __global__ __launch_bounds__(256) void cgs1_lag32_kernel(const double* __restric
     double acc[KC2][2];
 #pragma unroll
     for (int c = 0; c < KC2; ++c) acc[c][0] = acc[c][1] = 0.0;
+    double accl = 0.0;                              // the deferred column's products (see cgs1_lag_kernel)
     double nacc = 0.0;
     for (int64_t rb = r0 + (int64_t)w * RU; rb < r1; rb += (int64_t)nw * RU) {
         const int64_t rl = rb + lane;
@@ -1198,12 +1204,8 @@ __global__ __launch_bounds__(256) void cgs1_lag32_kernel(const double* __restric
 #pragma unroll
             for (int c = 0; c < KC2; ++c)
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    if (c == cl && lane == ll && h == hlf) y[u][c][h] = yl;
-#pragma unroll
-            for (int c = 0; c < KC2; ++c)
-#pragma unroll
                 for (int h = 0; h < 2; ++h) acc[c][h] = fma(y[u][c][h], v, acc[c][h]);
+            accl = fma(lane == ll ? yl : 0.0, v, accl);
             if (lane == u) { vo = v; yo = yl; }
             if (ju == u) yb7 = yl;
         }
@@ -1214,6 +1216,11 @@ __global__ __launch_bounds__(256) void cgs1_lag32_kernel(const double* __restric
         }
         if (okb) Y[(rb + ju) * ldy + yb + jj] = (float)(jj < 7 ? sv : yb7);
     }
+#pragma unroll
+    for (int c = 0; c < KC2; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (c == cl && h == hlf) acc[c][h] += accl;
     const double nn = block_sum(nacc, sred);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ldp + d] = nn;
     if (d == 0) return;
