@@ -69,6 +69,11 @@ def parse():
                          "fixed from a tol-0 fit, G ~ N(0,1)")
     ap.add_argument("--no-classify", action="store_true",
                     help="skip recognition of 262144 generated queries in compressed coordinates")
+    ap.add_argument("--rows-reps", type=int, default=20,
+                    help="timed passes of the backward and recognition rows (at least --steps; a pass takes "
+                         "a few ms, so three would time little more than launch overhead)")
+    ap.add_argument("--rows-warmup", type=int, default=5,
+                    help="untimed passes before them (at least --warmup)")
     ap.add_argument("--spd", action="store_true",
                     help="also time the general SPD A-norm fit (A = I + grid Laplacian) on the FP32 field")
     ap.add_argument("--weighted", action="store_true",
@@ -412,7 +417,8 @@ def backward_section(rbd, K, W, m=65536, n=2048, d=128, cpu=True, cpu_rows=8192)
                         "unit": "TFLOP/s", "frac": round(flops / sec / 78.6e12, 4),
                         "algorithmic_GFLOP": round(flops / 1e9, 2),
                         "note": "8mnd + 6md^2 algorithmic flops, FP64 matrix cores (78.6 TFLOP/s dense FP64)"},
-           "reconstruct_ms": round(fsec * 1e3, 3), "reconstruct_TFLOPs": round(2.0 * m * n * d / fsec / 1e12, 2)}
+           "reconstruct_ms": round(fsec * 1e3, 3), "reconstruct_TFLOPs": round(2.0 * m * n * d / fsec / 1e12, 2),
+           "timed_passes": K, "warmup_passes": W}
     if cpu:
         import oracle
         try:
@@ -472,7 +478,7 @@ def classify_section(rbd, K, W, k=262144, d_max=40, cpu=True):
     out = {"workload": f"view classes: 20 classes, {m} pixels (112 x 92), {n} training views, "
                        f"{k} generated query views (FP32)", "d": d, "queries": k,
            "value": round(k / sec, 1), "unit": "queries/s", "ms": round(sec * 1e3, 3),
-           "accuracy": round(acc, 4),
+           "accuracy": round(acc, 4), "timed_passes": K, "warmup_passes": W,
            "roofline": {"bound": "mfma", "achieved": round(flops / sec / 1e12, 2), "peak": 78.6, "unit": "TFLOP/s",
                         "frac": round(flops / sec / 78.6e12, 4), "algorithmic_GFLOP": round(flops / 1e9, 1),
                         "note": "2 m d k flops of the projection Y'V (FP64 matrix cores); the query stream is "
@@ -718,12 +724,13 @@ def next_rows(rbd, args):
         out["batched"] = batched_section(rbd, args.batch_count, args.steps, args.warmup, cache=args.batched_cache)
         if not args.no_cpu_baseline:
             out["batched"]["cpu_baseline"] = batched_cpu_baseline(args.batch_count)
+    reps, warm = max(args.steps, args.rows_reps), max(args.warmup, args.rows_warmup)
     if not args.no_backward:
         torch.cuda.empty_cache()
-        out["backward"] = backward_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        out["backward"] = backward_section(rbd, reps, warm, cpu=not args.no_cpu_baseline)
     if not args.no_classify:
         torch.cuda.empty_cache()
-        out["recognition"] = classify_section(rbd, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        out["recognition"] = classify_section(rbd, reps, warm, cpu=not args.no_cpu_baseline)
     return out
 
 

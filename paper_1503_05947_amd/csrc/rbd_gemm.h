@@ -44,12 +44,12 @@ struct GemmShape {
 // colrank[j] >= 0 and zero elsewhere, i.e. output column j gains column
 // colrank[j] of A2 (M x n2, leading dimension ld2).  colrank has N + 1 entries
 // and is increasing in the sense that a column's rank, or -1 - (its insertion
-// point) for columns that gain nothing, never decreases with j, so a tile's
-// columns gain the contiguous range of A2's columns [lo, hi) decoded from
-// colrank[col0] and colrank[col0 + 128]: they run as extra k-steps of the
-// tile, with E generated in place.  Products by exact zeros and ones add
-// nothing else, so each gaining entry is (A B)(i, j) + A2(i, colrank[j]) with
-// one rounding.
+// point) for columns that gain nothing, never decreases with j, so a wave's
+// 64 columns gain the contiguous range of A2's columns [lo_w, hi_w) decoded
+// from colrank at its first column and the one past its last: they run as
+// extra k-steps of the wave, with E generated in place.  Products by exact
+// zeros and ones add nothing else (each column has at most one rank), so each
+// gaining entry is (A B)(i, j) + A2(i, colrank[j]) with one rounding.
 struct GemmColAdd {
     const double* a2 = nullptr;
     int64_t ld2 = 0;
@@ -101,28 +101,40 @@ __global__ __launch_bounds__(256, GemmShape<WM>::WG_PER_CU) void gemm_f64_kernel
             rb[q] = (gj < N && gk < ke) ? (TB ? B[gj * ldb + gk] : B[gk * ldb + gj]) : TBe{};
         }
     };
-    // the extra columns (see GemmColAdd): A2's first chunk is loaded into the A
-    // registers during the last chunk of the product, like any next chunk
-    constexpr bool kPrefetchAdd = ADD && !TA && std::is_same<TAe, double>::value;
+    // the extra columns (see GemmColAdd): each wave adds A2's columns
+    // [lo_w, hi_w), those its own 64 columns gain, as extra k-steps taken from
+    // registers, with no LDS and no barrier: each lane loads its MFMA operands of
+    // A2 itself (the first kAddPre k-steps during the tile's last chunk) and
+    // forms E's from the rank of its column
     auto dec = [](int r) { return r >= 0 ? r : -1 - r; };
-    int lo = 0, hi = 0;
+    int lo_w = 0, hi_w = 0;
     if (ADD) {
-        lo = dec(add.colrank[min(col0, N)]);
-        hi = dec(add.colrank[min(col0 + kGN, N)]);
+        lo_w = dec(add.colrank[min(col0 + wc, N)]);
+        hi_w = dec(add.colrank[min(col0 + wc + 64, N)]);
     }
-    auto load_add = [&](int k0) {       // A2(row0 .. row0 + kGM - 1, k0 .. k0 + kGK - 1), zero past hi
+    constexpr int kAddPre = 2;
+    double pa[kAddPre][MT];
+    int cr[4];
+    auto load_add = [&](int s, double (&v)[MT]) {      // k-step s: ranks lo_w + 4 s + (0 .. 3)
+        const int r = lo_w + 4 * s + lane / 16;
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-            const int e = tid + 256 * q;
-            const int i = e / kGK, k = e % kGK;
-            const int64_t gi = row0 + i;
-            const double v = (gi < M && k0 + k < hi) ? add.a2[gi * add.ld2 + k0 + k] : 0.0;
-            if constexpr (kPrefetchAdd) ra[q] = v;
-            else As[k][i] = v;
+        for (int a = 0; a < MT; ++a) {
+            const int64_t gi = row0 + wr + a * 16 + lane % 16;
+            v[a] = (gi < M && r < hi_w) ? add.a2[gi * add.ld2 + r] : 0.0;
         }
     };
-    if (kb < ke) load(kb);
-    for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
+    auto prefetch_add = [&]() {
+#pragma unroll
+        for (int q = 0; q < kAddPre; ++q) load_add(q, pa[q]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t gj = col0 + wc + b * 16 + lane % 16;
+            cr[b] = gj < N ? add.colrank[gj] : -1;
+        }
+    };
+    // one chunk: stage the operands loaded one chunk earlier, then load the
+    // next chunk's (LAST: the extra columns' instead) while multiplying
+    auto chunk = [&](int64_t k0, auto last) {
         __syncthreads();      // the previous chunk's products are done with LDS
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -137,8 +149,8 @@ __global__ __launch_bounds__(256, GemmShape<WM>::WG_PER_CU) void gemm_f64_kernel
             else Bs[e / kGN][e % kGN] = Ld<TBe>::from(rb[q]);
         }
         __syncthreads();
-        if (k0 + kGK < ke) load(k0 + kGK);
-        else if (kPrefetchAdd && lo < hi) load_add(lo);
+        if constexpr (!decltype(last)::value) load(k0 + kGK);
+        else if (ADD && lo_w < hi_w) prefetch_add();
 #pragma unroll
         for (int ks = 0; ks < kGK; ks += 4) {
             double af[MT], bf[4];
@@ -152,53 +164,34 @@ __global__ __launch_bounds__(256, GemmShape<WM>::WG_PER_CU) void gemm_f64_kernel
                 for (int b = 0; b < 4; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
-    }
-    if (ADD) {
-        // this wave's 64 columns gain [lo_w, hi_w): it multiplies only the k-steps that meet it
-        const int lo_w = dec(add.colrank[min(col0 + wc, N)]), hi_w = dec(add.colrank[min(col0 + wc + 64, N)]);
-        for (int k0 = lo; k0 < hi; k0 += kGK) {
-            const bool pre = kPrefetchAdd && k0 == lo && kb < ke;      // already in ra
-            __syncthreads();
-            if (pre) {
+    };
+    // the last chunk peeled off, so that what it prefetches for the extra
+    // columns is not live across the loop
+    int64_t k0 = kb;
+    if (kb < ke) load(kb);
+    for (; k0 + kGK < ke; k0 += kGK) chunk(k0, std::false_type{});
+    if (k0 < ke) chunk(k0, std::true_type{});
+    if (ADD && lo_w < hi_w) {
+        if (!(kb < ke)) prefetch_add();               // no chunk of the product to hide it behind
+        auto mul = [&](const double (&af)[MT], int s) {
+            const int r = lo_w + 4 * s + lane / 16;
+            double bf[4];
 #pragma unroll
-                for (int q = 0; q < QA; ++q) {
-                    const int e = tid + 256 * q;
-                    As[e % kGK][e / kGK] = Ld<TAe>::from(ra[q]);
-                }
-            } else {
-                if constexpr (kPrefetchAdd) {
-                    load_add(k0);
+            for (int b = 0; b < 4; ++b) bf[b] = cr[b] == r ? 1.0 : 0.0;
 #pragma unroll
-                    for (int q = 0; q < QA; ++q) {
-                        const int e = tid + 256 * q;
-                        As[e % kGK][e / kGK] = Ld<TAe>::from(ra[q]);
-                    }
-                } else {
-                    load_add(k0);
-                }
-            }
+            for (int a = 0; a < MT; ++a)
 #pragma unroll
-            for (int q = 0; q < (kGN * kGK) / 256; ++q) {
-                const int e = tid + 256 * q;
-                const int k = e / kGN, j = e % kGN;
-                const int64_t gj = col0 + j;
-                Bs[k][j] = (gj < N && add.colrank[gj] == k0 + k) ? 1.0 : 0.0;
-            }
-            __syncthreads();
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        };
+        const int nsteps = (hi_w - lo_w + 3) / 4;
 #pragma unroll
-            for (int ks = 0; ks < kGK; ks += 4) {
-                if (k0 + ks + 4 <= lo_w || k0 + ks >= hi_w) continue;      // wave-uniform
-                double af[MT], bf[4];
-#pragma unroll
-                for (int a = 0; a < MT; ++a) af[a] = As[ks + lane / 16][wr + a * 16 + lane % 16];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + lane / 16][wc + b * 16 + lane % 16];
-#pragma unroll
-                for (int a = 0; a < MT; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
-            }
+        for (int q = 0; q < kAddPre; ++q)
+            if (q < nsteps) mul(pa[q], q);
+        for (int q = kAddPre; q < nsteps; ++q) {
+            double af[MT];
+            load_add(q, af);
+            mul(af, q);
         }
     }
     double* out = part ? part + (int64_t)blockIdx.z * M * N : nullptr;
