@@ -377,9 +377,12 @@ constexpr int kY32Switch = 128;
 constexpr int kc2_of(int KC) { return KC <= 2 ? 1 : KC / 2; }
 constexpr int rows32(int KC) { return kc2_of(KC) <= 2 ? 8 : (kc2_of(KC) <= 4 ? 4 : 2); }
 
-template <int KC, typename Tb>
-void launch_cgs1_lag(const FitPlan& P, const double* xp, Tb* Y, const double* T, State* st, int d,
-                     const double* v1p, const double* h2p, double* v1, double* ys, double* part, hipStream_t s) {
+// The FP64-basis pass reads x_p from X itself; the FP32-basis pass reads the
+// column gathered into xp (reading X there measured slower).
+template <int KC, typename Tb, typename Tx>
+void launch_cgs1_lag(const FitPlan& P, const Tx* X, int64_t ldx, const double* xp, Tb* Y, const double* T, State* st,
+                     int d, const double* v1p, const double* h2p, double* v1, double* ys, double* part,
+                     hipStream_t s) {
     if constexpr (std::is_same<Tb, float>::value) {
         constexpr int K2 = kc2_of(KC), R2 = rows32(KC);
         if (y_stream(P, d))
@@ -389,11 +392,11 @@ void launch_cgs1_lag(const FitPlan& P, const double* xp, Tb* Y, const double* T,
             cgs1_lag32_kernel<K2, R2, false><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.ldyf, T, P.n, st, d, P.cg_rows, v1p,
                                                                      h2p, v1, ys, part, std::max(P.D, 1));
     } else if (y_stream(P, d)) {
-        cgs1_lag_kernel<KC, rows_in_flight(KC), true, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+        cgs1_lag_kernel<KC, rows_in_flight(KC), true, Tb, Tx><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
                                                                               P.cg_rows, v1p, h2p, v1, ys, part,
                                                                               std::max(P.D, 1));
     } else {
-        cgs1_lag_kernel<KC, rows_in_flight(KC), false, Tb><<<P.cg_S, 256, 0, s>>>(xp, P.m, Y, P.d_max, T, P.n, st, d,
+        cgs1_lag_kernel<KC, rows_in_flight(KC), false, Tb, Tx><<<P.cg_S, 256, 0, s>>>(X, ldx, P.m, Y, P.d_max, T, P.n, st, d,
                                                                                P.cg_rows, v1p, h2p, v1, ys, part,
                                                                                std::max(P.D, 1));
     }
@@ -558,14 +561,17 @@ int fit_typed(const FitPlan& P, const Tx* X, int64_t ldx, double tol, int rel, i
             const int c = d & 1;
             const int kc = kc_for(d);
             prof_begin(RBD_PHASE_CGS1, s);
-            launch_gather<Tx>(P, X, ldx, st, xp, s);
-            RBD_LAUNCH_CHECK();
+            // the FP64-basis pass reads x_p from X itself; the FP32-basis pass takes it gathered
+            if constexpr (std::is_same<Tb, float>::value) {
+                launch_gather<Tx>(P, X, ldx, st, xp, s);
+                RBD_LAUNCH_CHECK();
+            }
             switch (kc) {
-                case 1: launch_cgs1_lag<1>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-                case 2: launch_cgs1_lag<2>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-                case 4: launch_cgs1_lag<4>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-                case 8: launch_cgs1_lag<8>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
-                default: launch_cgs1_lag<16>(P, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 1: launch_cgs1_lag<1>(P, X, ldx, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 2: launch_cgs1_lag<2>(P, X, ldx, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 4: launch_cgs1_lag<4>(P, X, ldx, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                case 8: launch_cgs1_lag<8>(P, X, ldx, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
+                default: launch_cgs1_lag<16>(P, X, ldx, xp, Yb, T, st, d, v1s[c ^ 1], h2s[c ^ 1], v1s[c], ys, part, s); break;
             }
             RBD_LAUNCH_CHECK();
             launch_sum_rows(st, part, std::max(P.D, 1), P.cg_S, P.cg_group, d + 1, l2, h2s[c], 0, s);

@@ -858,8 +858,8 @@ __global__ __launch_bounds__(256) void cgs2u_kernel(double* __restrict__ Y, int6
 // stages it, then v1 = x_p - Y(:, 0:d) h1 (h1 = T(0:d, p)); per block the
 // share of h2 = Y(:, 0:d)' v1 (part[blk*ldp + k], k < d) and of ||v1||^2
 // (part[blk*ldp + d]).
-template <int KC, int RU, bool NT, typename Tb = double>
-__global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict__ xp, int64_t m,
+template <int KC, int RU, bool NT, typename Tb, typename Tx>
+__global__ __launch_bounds__(256) void cgs1_lag_kernel(const Tx* __restrict__ X, int64_t ldx, int64_t m,
                                                         Tb* __restrict__ Y, int64_t ldy,
                                                         const double* __restrict__ T, int64_t ldt,
                                                         State* __restrict__ st, int d, int rows_per_blk,
@@ -903,13 +903,16 @@ __global__ __launch_bounds__(256) void cgs1_lag_kernel(const double* __restrict_
         // lane u < RU carries row rb + u's scalars (one load / store instruction per group)
         const int64_t rl = rb + lane;
         const bool okl = lane < RU && rl < r1;
-        const double xl = okl ? xp[rl] : 0.0;
+        // x_p's entries straight from X, widened after the group's other loads
+        // have issued (a widening under the test would wait for the load)
+        const Tx xr = okl ? X[rl * ldx + p] : Tx{};
         const double vl = (okl && dl >= 0) ? v1p[rl] : 0.0;
         const bool okb = blk && ju < RU && rb + ju < r1;
         const Tb sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : Tb(0);
         double y[RU][KC];
         double dots[2 * RU];
         load_y_rows<NT, RU, KC>(y, Y, ldy, ys, m, rb, r1, lane, dl, yb);
+        const double xl = Ld<Tx>::from(xr);
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             double a = 0.0, b = 0.0;
