@@ -429,7 +429,7 @@ int rbd_classify(const double* Y, int64_t ldy, int64_t m, int32_t d, const doubl
 enum {
     RBD_PHASE_COLNORM = 0,   /* diag(X'X) pre-computation (section 3.3)          */
     RBD_PHASE_INIT = 1,      /* E_0, tau, first column                           */
-    RBD_PHASE_CGS1 = 2,      /* pivot gather, first pass over Y, partial h2       */
+    RBD_PHASE_CGS1 = 2,      /* the pass over Y (x_p read from X, or gathered)   */
     RBD_PHASE_CGS2 = 3,      /* nu and the break test; for A = I the correction   *
                               * rows of T, otherwise the second pass over Y and   *
                               * the A-norm terms                                  */
