@@ -77,6 +77,9 @@ def test_layouts_and_starts(monkeypatch):
     w = synth.bump_field(3, m=300, n=257)
     stored, vals = synth.quantize(w.X, "f32")
     check_both(monkeypatch, "ldx = n + 3", stored, vals, "f32", 1e-3, 60, rel=True, pad_cols=3)
+    # 2-byte entries at an odd leading dimension: the per-kernel driver's pass over Y reads x_p from X itself
+    stored16, vals16 = synth.quantize(w.X, "bf16")
+    check_both(monkeypatch, "bf16 ldx = n + 5", stored16, vals16, "bf16", 1e-2, 40, rel=True, pad_cols=5)
     check_both(monkeypatch, "start = 200", stored, vals, "f32", 0.0, 30, start=200, exact_d=False)
 
 
