@@ -1099,7 +1099,10 @@ __global__ __launch_bounds__(256) void ycol_kernel(Tb* __restrict__ Y, int64_t l
 // Entries (rb + u, k) and (rb + u, k + 1), k = 2 lane + 128 c, widened to
 // FP64; zero for rows >= r1 or columns >= cols.  Loads from clamped
 // addresses, all issued before the first widening.
-template <bool NT, int RU, int KC2>
+// FREE: the caller's KC2 is the one the host sizes from the step (kc2_of(kc_for(d))
+// with cols = d - 1, yb = cols rounded down to 8), so the chunks below KC2 / 2 lie
+// wholly below yb and take no select; rows past r1 are zeroed by one uniform test.
+template <bool NT, int RU, int KC2, bool FREE = false>
 __device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const float* Y, int64_t ldy,
                                               const double* ys, int64_t m, int64_t rb, int64_t r1, int lane,
                                               int cols, int yb) {
@@ -1121,10 +1124,16 @@ __device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const flo
         s1[u] = in_st ? ys[(ks + 1) * m + r] : 0.0;
     }
     __builtin_amdgcn_sched_barrier(0);              // every load above issues before the first use below
+    constexpr int kFree = FREE ? KC2 / 2 : 0;
 #pragma unroll
-    for (int u = 0; u < RU; ++u)
+    for (int u = 0; u < RU; ++u) {
 #pragma unroll
-        for (int c = 0; c < KC2; ++c) {
+        for (int c = 0; c < kFree; ++c) {
+            y[u][c][0] = (double)raw[u][c].x;
+            y[u][c][1] = (double)raw[u][c].y;
+        }
+#pragma unroll
+        for (int c = kFree; c < KC2; ++c) {
             const int k = 2 * lane + 128 * c;
             const bool ok = rb + u < r1;
             const bool st = k >= yb;                    // a staged pair (it lies in chunk cyb)
@@ -1132,6 +1141,15 @@ __device__ __forceinline__ void load_y32_rows(double (&y)[RU][KC2][2], const flo
             y[u][c][0] = (ok && k < cols) ? a : 0.0;
             y[u][c][1] = (ok && k + 1 < cols) ? b : 0.0;
         }
+    }
+    if (kFree > 0 && rb + RU > r1) {
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (rb + u >= r1) {
+#pragma unroll
+                for (int c = 0; c < kFree; ++c) y[u][c][0] = y[u][c][1] = 0.0;
+            }
+    }
 }
 
 // cgs1_lag for an FP32 basis: the arithmetic of cgs1_lag_kernel, the deferred
@@ -1183,7 +1201,7 @@ __global__ __launch_bounds__(256) void cgs1_lag32_kernel(const double* __restric
         const double sv = (okb && jj < 7) ? ys[(int64_t)jj * m + rb + ju] : 0.0;
         double y[RU][KC2][2];
         double dots[2 * RU];
-        load_y32_rows<NT, RU, KC2>(y, Y, ldy, ys, m, rb, r1, lane, dl, yb);
+        load_y32_rows<NT, RU, KC2, true>(y, Y, ldy, ys, m, rb, r1, lane, dl, yb);
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             double a = 0.0, b = 0.0;
