@@ -238,6 +238,44 @@ static __global__ __launch_bounds__(256) void gemm_split_sum_kernel(int64_t M, i
     }
 }
 
+// The same sums for outputs too small to fill the GPU with one thread per
+// entry: the eight chains of an entry run on eight adjacent threads, and the
+// chain sums are added in the same order from LDS (bit-identical results).
+static __global__ __launch_bounds__(256) void gemm_split_sum8_kernel(int64_t M, int64_t N, int splits, double alpha,
+                                                               const double* __restrict__ part, double beta,
+                                                               double* __restrict__ C, int64_t ldc) {
+    __shared__ double gs[256];
+    const int64_t tot = M * N;
+    const int u = threadIdx.x % 8;
+    const int64_t e = (int64_t)blockIdx.x * 32 + threadIdx.x / 8;
+    double g = 0.0;
+    if (e < tot) {
+#pragma unroll 4
+        for (int q = u; q < splits; q += 8) g += part[(int64_t)q * tot + e];
+    }
+    gs[threadIdx.x] = g;
+    __syncthreads();
+    if (u == 0 && e < tot) {
+        double sum = 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) sum += gs[threadIdx.x + v];
+        const int64_t i = e / N, j = e % N;
+        const double prev = beta != 0.0 ? C[i * ldc + j] : 0.0;
+        C[i * ldc + j] = alpha * sum + beta * prev;
+    }
+}
+
+// C = alpha * sum of the split partials + beta * C (either kernel above)
+inline void launch_split_sum(int64_t M, int64_t N, int splits, double alpha, const double* part, double beta,
+                             double* C, int64_t ldc, hipStream_t s) {
+    const int64_t tot = M * N;
+    if (tot <= 65536)
+        gemm_split_sum8_kernel<<<(unsigned)((tot + 31) / 32), 256, 0, s>>>(M, N, splits, alpha, part, beta, C, ldc);
+    else
+        gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, (tot + 255) / 256), 256, 0, s>>>(
+            M, N, splits, alpha, part, beta, C, ldc);
+}
+
 constexpr size_t kPartElems = (size_t)8 << 20;   // split-k partials: 64 MB
 
 // Host side: C = alpha op(A) op(B) + beta C.  The k range is split (partials
@@ -274,11 +312,7 @@ inline hipError_t gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const 
     else
         gemm_f64_kernel<TA, TB, TAe, TBe><<<grid, 256, 0, s>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk,
                                                                 splits > 1 ? part : nullptr, add);
-    if (splits > 1) {
-        const int64_t tot = M * N;
-        gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, cdiv(tot, 256)), 256, 0, s>>>(
-            M, N, (int)splits, alpha, part, beta, C, ldc);
-    }
+    if (splits > 1) launch_split_sum(M, N, (int)splits, alpha, part, beta, C, ldc, s);
     return hipGetLastError();
 }
 

@@ -188,11 +188,7 @@ inline hipError_t proj_mfma(const double* Y, int64_t ldy, int64_t m, int d, cons
     // one launch: rows past d are skipped inside, so MT = 4 serves every full row tile and
     // the narrower last tile only matters when it is the only one
     launch(rtiles == 1 ? mt_last : 4, grid, 0);
-    if (splits > 1) {
-        const int64_t tot = (int64_t)d * N;
-        gemm_split_sum_kernel<<<(unsigned)std::min<int64_t>(4096, proj_cdiv(tot, 256)), 256, 0, s>>>(
-            d, N, (int)splits, 1.0, part, 0.0, C, ldc);
-    }
+    if (splits > 1) launch_split_sum(d, N, (int)splits, 1.0, part, 0.0, C, ldc, s);
     return hipGetLastError();
 }
 
