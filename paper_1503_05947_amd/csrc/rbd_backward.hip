@@ -195,8 +195,11 @@ int backward_typed(const BwdPlan& P, const Tx* X, int64_t ldx, const Tg* G, int6
     ok(gemm<false, false, double, double>(m, d, d, 1.0, Y, ldy, S, d, 1.0, Ybar, d, nullptr, 0, s));
     // Rinv' = R^{-1}, rows in pivot-rank order (R gathered once by pivot_rank_kernel when d <= kRinvLds)
     const bool lds_inv = d <= kRinvLds;
-    pivot_rank_kernel<<<(unsigned)cd(std::max<int64_t>(n + 1, d), 256), 256, 0, s>>>(piv, d, n, colrank, rank, T,
-                                                                                     ldt, lds_inv ? Rp : nullptr);
+    // one thread per column rank, pivot rank and (with the LDS inverse) entry of the packed R
+    const int64_t rank_threads =
+        std::max<int64_t>(std::max<int64_t>(n + 1, d), lds_inv ? (int64_t)d * (d + 1) / 2 : 0);
+    pivot_rank_kernel<<<(unsigned)cd(rank_threads, 256), 256, 0, s>>>(piv, d, n, colrank, rank, T, ldt,
+                                                                       lds_inv ? Rp : nullptr);
     ok(hipGetLastError());
     if (lds_inv) {
         const size_t lds = sizeof(double) * ((size_t)d * (d + 1) / 2 + d);
